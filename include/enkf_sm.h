@@ -1,0 +1,198 @@
+/*
+ * enkf_sm.h -- C ABI of the MI355X (gfx950) EnKF analysis library.
+ *
+ * The library computes the analysis step of the ensemble Kalman filter with
+ * the iterative Sherman-Morrison formula of Nino-Ruiz, Sandu and Anderson,
+ * "An efficient implementation of the ensemble Kalman filter based on an
+ * iterative Sherman-Morrison formula" (Statistics and Computing, 2014):
+ *
+ *   D  = Y - H X^B,  V = H S,  S = (X^B - xbar 1^T) / sqrt(N-1)    (Section 3, eq. system-rewritten)
+ *   Z  = S*(R, V, D), i.e. (R + V V^T) Z = D, R diagonal          (Section 3.1, Steps 1-2)
+ *   X^A = X^B + S (V^T Z)                                         (Section 3.1, the SMEnKF listing)
+ *
+ * Conventions for every call:
+ *   - Matrices are column-major, one column per ensemble member: element
+ *     (i, j) of a matrix with leading dimension ld sits at p[i + j*ld].
+ *   - Every data pointer is a DEVICE pointer (hipMalloc'd or a torch CUDA
+ *     tensor's data_ptr) unless the argument says HOST.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Every call only enqueues work on that stream and returns; nothing is
+ *     synchronised unless the argument list says so.
+ *   - The caller owns every buffer it passes. A plan borrows the r and V
+ *     pointers given to enkf_sm_init: they must stay valid and unchanged until
+ *     enkf_sm_destroy. A plan owns its workspace (allocated in enkf_sm_init).
+ *   - Every call returns an enkf_status. Argument errors are found on the host
+ *     before anything is launched. Errors found by kernels (a pivot gamma_k not
+ *     finite or not > 0, an r_i not finite or not > 0) are latched in a device
+ *     status word of the plan and returned by the next synchronising call
+ *     (enkf_sm_solve with info != NULL, or enkf_sm_get_info).
+ *   - A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef ENKF_SM_H
+#define ENKF_SM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ENKF_SUCCESS = 0,
+    ENKF_ERR_INVALID_ARG = 1,     /* bad shape, leading dimension, pointer or option */
+    ENKF_ERR_NOT_SPD = 2,         /* r_i <= 0 / non-finite, or gamma_k <= 0 / non-finite (Section 3.3) */
+    ENKF_ERR_NO_CONVERGENCE = 3,  /* refinement stopped above its tolerance; Z holds the last iterate */
+    ENKF_ERR_HIP = 4,             /* a HIP runtime call failed */
+    ENKF_ERR_OUT_OF_MEMORY = 5,   /* workspace allocation failed */
+    ENKF_ERR_NOT_SUPPORTED = 6    /* valid but unsupported combination of options */
+} enkf_status;
+
+/* Storage type of V, D, Z, X^B and X^A as the caller passes them. */
+typedef enum { ENKF_F64 = 0, ENKF_F32 = 1 } enkf_dtype;
+
+/* ENKF_SM_PLAIN: the level-by-level iteration of Section 3.1 (Step 2), one
+ *   pass over the active columns per level k = 1..N.
+ * ENKF_SM_BLOCKED: the same levels taken b at a time. A panel K of b levels
+ *   applies the Sherman-Morrison-Woodbury identity (eq. SWM) with a rank-b
+ *   term: X <- X - U_K M_K^{-1} (V_K^T X), M_K = I + V_K^T U_K, whose LDL^T
+ *   pivots are exactly the gamma_k of the b levels. */
+typedef enum { ENKF_SM_PLAIN = 0, ENKF_SM_BLOCKED = 1 } enkf_sm_algo;
+
+/* Input type of the blocked panel products V^T U, V^T X and U Q on the matrix
+ * cores. A type narrower than `dtype` makes the solve mixed precision: the
+ * plan keeps an FP32 copy of V and of the factor, the panel products run in
+ * `math`, the b x b panel pivots stay FP64, and enkf_sm_solve refines Z with
+ * FP64 residuals D - (R Z + V (V^T Z)). The X2/X3 forms split each FP32
+ * operand into a high and a low 16-bit part and sum the cross products. */
+typedef enum {
+    ENKF_MATH_F64 = 0,
+    ENKF_MATH_F32 = 1,
+    ENKF_MATH_BF16 = 2,
+    ENKF_MATH_F16 = 3,
+    ENKF_MATH_BF16X3 = 4,
+    ENKF_MATH_F16X2 = 5
+} enkf_math;
+
+/* Pivoting of Section 3.4 (eq. gamma-value): before level k the remaining
+ * column with the largest gamma is swapped into position k. Plain only. */
+#define ENKF_FLAG_PIVOT 0x1u
+
+typedef struct {
+    int64_t n_obs;          /* n >= 1 */
+    int32_t n_ens;          /* N >= 1 */
+    enkf_dtype dtype;
+    enkf_sm_algo algo;
+    enkf_math math;         /* must be ENKF_MATH_F64 for PLAIN F64, ENKF_MATH_F32 for PLAIN F32 */
+    int32_t block;          /* panel width b for BLOCKED (1..N); 0 = pick one */
+    int32_t max_nrhs;       /* largest nrhs a solve may pass; 0 = n_ens */
+    int32_t refine_max_iter;/* mixed precision: maximum refinement steps (0 = none) */
+    double refine_tol;      /* mixed precision: stop when ||D - W Z||_F / ||D||_F <= tol */
+    uint32_t flags;         /* ENKF_FLAG_* */
+} enkf_sm_desc;
+
+typedef struct {
+    int32_t refine_iters;   /* refinement steps taken by the last solve */
+    double rel_residual;    /* ||D - W Z||_F / ||D||_F of the last solve (mixed, or when computed) */
+    double gamma_min;       /* smallest and largest pivot gamma_k of the factor */
+    double gamma_max;
+    int32_t device_status;  /* enkf_status latched by kernels (0 = none) */
+} enkf_sm_info;
+
+typedef struct enkf_sm_plan_s* enkf_sm_plan;
+
+/* Host-only check of a descriptor (no GPU needed). */
+enkf_status enkf_sm_validate_desc(const enkf_sm_desc* desc);
+
+/*
+ * Build the inputs of the solve from the background ensemble (Section 2 and
+ * Section 3, eqs. EnSM:Matrix-member-deviations, system-rhs,
+ * member-observations), with H the row selection x -> x[obs_idx]:
+ *   xbar_s = (1/N) sum_j X^B[s, j]
+ *   V[i, j] = (X^B[obs_idx[i], j] - xbar_{obs_idx[i]}) / sqrt(N - 1)
+ *   D[i, j] = (y[i] + E[i, j]) - X^B[obs_idx[i], j]
+ * XB (n_state x N, ldx >= n_state), obs_idx (n_obs, int64, 0 <= idx < n_state),
+ * y (n_obs, FP64), E (n_obs x N, lde >= n_obs, perturbations ~ N(0, R), in
+ * `dtype`), V and D (n_obs x N, ldv >= n_obs, in `dtype`). N >= 2.
+ * Out-of-range obs_idx entries are not checked on the host (they live on the
+ * device); the kernel clamps nothing and the caller must pass valid indices.
+ */
+enkf_status enkf_build_vd(int64_t n_state, int32_t n_ens, enkf_dtype dtype, const void* XB, int64_t ldx,
+                          const int64_t* obs_idx, int64_t n_obs, const double* y, const void* E, int64_t lde,
+                          void* V, void* D, int64_t ldv, void* stream);
+
+/*
+ * Create a plan and run the D-independent half of S*(R, V, D): Step 1 for V
+ * (U0 = R^{-1} V) and the U-updates of every level (eq. SM-step-2-u), which
+ * leave the factor {u_k^{(k-1)}, gamma_k} (blocked: {U_K, M_K} per panel).
+ * r (n_obs, FP64, each > 0) and V (n_obs x N, ldv >= n_obs, `desc->dtype`)
+ * are borrowed until enkf_sm_destroy. Allocates the workspace, so it must not
+ * be called under stream capture.
+ */
+enkf_status enkf_sm_init(enkf_sm_plan* out, const enkf_sm_desc* desc, const double* r, const void* V,
+                         int64_t ldv, void* stream);
+
+/*
+ * Recompute the factor of an existing plan for a new (r, V) of the same shape
+ * and type, reusing its workspace (the next analysis cycle): the same work as
+ * enkf_sm_init without any allocation. Clears the latched status word. The
+ * new r and V are borrowed as in enkf_sm_init.
+ */
+enkf_status enkf_sm_refactor(enkf_sm_plan plan, const double* r, const void* V, int64_t ldv);
+
+/*
+ * The D-dependent half of S*: Step 1 for D (Z0 = R^{-1} D) and the Z-updates
+ * of every level (eq. SM-step-2-Z): Z = (R + V V^T)^{-1} D.
+ * D and Z are n_obs x nrhs (nrhs >= 0; the analysis has nrhs = N) in the
+ * plan's dtype; Z may alias D only if ldz == ldd. Allocates nothing.
+ * info == NULL: asynchronous, refinement (if any) runs exactly
+ *   refine_max_iter steps. info != NULL: synchronises the plan's stream,
+ *   stops refinement at refine_tol, fills *info and returns latched errors.
+ */
+enkf_status enkf_sm_solve(enkf_sm_plan plan, int32_t nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz,
+                          enkf_sm_info* info);
+
+/*
+ * Analysis update X^A = X^B + S (V^T Z) with S = (X^B - xbar 1^T)/sqrt(N-1)
+ * (Section 3.1), using the plan's V. XB and XA are n_state x N (ldx, ldxa >=
+ * n_state) in the plan's dtype; Z is n_obs x N (ldz >= n_obs). XA must not
+ * overlap XB (checked on the host). N >= 2. Allocates nothing.
+ */
+enkf_status enkf_analysis(enkf_sm_plan plan, int64_t n_state, const void* XB, int64_t ldx, const void* Z,
+                          int64_t ldz, void* XA, int64_t ldxa);
+
+/* Synchronise the plan's stream and report the factor's pivots, the last
+ * solve's refinement record and any latched device error. */
+enkf_status enkf_sm_get_info(enkf_sm_plan plan, enkf_sm_info* info);
+
+/* Copy the pivots gamma_1..gamma_N (FP64, HOST buffer of n_ens entries) and,
+ * when pivoting, the level order (HOST int32 buffer or NULL: entry k is the V
+ * column used at level k). Synchronises. */
+enkf_status enkf_sm_get_pivots(enkf_sm_plan plan, double* gamma_host, int32_t* perm_host);
+
+/*
+ * Measurement: when enabled, the plan records a HIP event pair on its stream
+ * around every kernel launch it makes and, per kernel class, accumulates the
+ * elapsed time, the number of launches and the algorithmic bytes and flops of
+ * those launches (the minimum each launch must move or compute; the byte and
+ * flop models are stated next to each kernel). Enabling or disabling clears
+ * the totals. enkf_sm_get_timing synchronises on the recorded events.
+ * Classes: 0 factor sweeps (plain), 1 solve sweeps (plain), 2 build,
+ * 3 analysis update, 4 split-K products, 5 panel updates (blocked),
+ * 6 panel factorisations (blocked), 7 FP64 residuals (refinement).
+ */
+enkf_status enkf_sm_set_timing(enkf_sm_plan plan, int32_t enable);
+enkf_status enkf_sm_get_timing(enkf_sm_plan plan, int32_t kernel_class, double* total_ms, int64_t* launches,
+                               double* alg_bytes, double* alg_flops);
+
+/* Release the workspace. Synchronises the plan's stream first. */
+void enkf_sm_destroy(enkf_sm_plan plan);
+
+const char* enkf_status_string(enkf_status s);
+/* Detail of the last error raised on the calling thread. */
+const char* enkf_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENKF_SM_H */

@@ -1,0 +1,120 @@
+// Internal declarations shared by the HIP sources of the library (not part
+// of the C ABI). gfx950 (CDNA4) only: wave64, 256 CUs in 8 XCDs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "enkf_sm.h"
+
+namespace enkf {
+
+constexpr int kWave = 64;
+
+// Device status word values (a subset of enkf_status).
+constexpr unsigned kStatusNotSpd = ENKF_ERR_NOT_SPD;
+
+// Kernel classes whose launches can be timed with HIP events (measurement).
+enum KernelClass : int {
+  KC_INIT_SWEEP = 0,   // plain: Step 1 + U-updates, one launch per level
+  KC_SOLVE_SWEEP = 1,  // plain: Step 1 + Z-updates, one launch per level
+  KC_BUILD = 2,        // V, D from the ensemble
+  KC_ANALYSIS = 3,     // X^A = X^B + S G (tall GEMM incl. mean)
+  KC_GRAM = 4,         // split-K products V^T X (analysis G, residual, panels)
+  KC_PANEL_UPDATE = 5, // blocked: X -= U_K Q (+ look-ahead products)
+  KC_PANEL_FACTOR = 6, // blocked: b x b LDL^T and solves
+  KC_RESIDUAL = 7,     // FP64 residual of the refinement
+  KC_COUNT = 8
+};
+
+void set_error(const std::string& msg);
+enkf_status fail(enkf_status s, const std::string& msg);
+const char* status_name(enkf_status s);
+
+#define ENKF_HIP_CHECK(expr)                                                              \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      return ::enkf::fail(ENKF_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// Records event pairs around launches of one kernel class and accumulates the
+// algorithmic bytes and flops those launches move (measurement only).
+struct Timing {
+  bool enabled = false;
+  struct Rec { int cls; hipEvent_t a, b; double bytes, flops; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[KC_COUNT] = {};
+  double bytes[KC_COUNT] = {};
+  double flops[KC_COUNT] = {};
+  int64_t launches[KC_COUNT] = {};
+  hipEvent_t get_event();
+  void begin(hipStream_t s, int cls, double bytes, double flops, hipEvent_t* a);
+  void end(hipStream_t s, hipEvent_t a, int cls, double bytes, double flops);
+  hipError_t harvest();  // synchronises on the recorded events
+  void reset();
+  ~Timing();
+};
+
+// RAII-free scope helper used around launches.
+struct TimedLaunch {
+  Timing* t; hipStream_t s; int cls; double by, fl; hipEvent_t a = nullptr;
+  TimedLaunch(Timing* t_, hipStream_t s_, int c, double b, double f) : t(t_), s(s_), cls(c), by(b), fl(f) {
+    if (t && t->enabled) t->begin(s, cls, by, fl, &a);
+  }
+  ~TimedLaunch() { if (t && t->enabled && a) t->end(s, a, cls, by, fl); }
+};
+
+// ---------------------------------------------------------------- plain sweeps
+// One level pass (or Step 1) over `m` columns of X. See level_kernels.hip.
+// The look-ahead products of a launch are left as per-block partials
+// ([column][row block] layout); every block of the next launch sums the
+// partials it needs itself, in row-block order, so no cross-block
+// synchronisation is needed inside a launch.
+struct LevelArgs {
+  int64_t n;
+  int vw;                               // elements per lane load (1, or 16 bytes' worth)
+  void* X; int64_t ldx; int m;          // active columns X[:, 0..m)
+  const void* uk;                       // u_k^{(k-1)} (level) or nullptr (Step 1)
+  const double* gamma_in;               // solve: &gamma[k]; factorisation: nullptr (formed from prev)
+  double* gamma_out;                    // factorisation: &gamma[k] written by block (0,0)
+  const double* prev;                   // partials of the previous launch ([col][nb]) or nullptr
+  int prev_m;                           // columns in prev
+  int prev_off;                         // active column q uses prev column q + prev_off
+  const void* vnext;                    // v_{k+1} or nullptr (no look-ahead products)
+  const double* r;                      // Step 1: diag(R)
+  const void* src; int64_t lds;         // Step 1: V or D
+  double* part_out;                     // this launch's partials ([m][nb])
+  unsigned* status;                     // device status word
+};
+
+enkf_status launch_level(enkf_dtype dt, const LevelArgs& a, hipStream_t s);
+// gamma[k] = 1 + sum of column `col` of partials (last level of a factorisation).
+enkf_status launch_gamma_from_partials(const double* part, int nb, int col, double* gamma_out, unsigned* status,
+                                       hipStream_t s);
+int level_row_blocks(enkf_dtype dt, int vw, int64_t n);
+int level_vw(enkf_dtype dt);
+
+// ---------------------------------------------------------------- build
+enkf_status launch_build_vd(enkf_dtype dt, int64_t n_state, int n_ens, const void* XB, int64_t ldx,
+                            const int64_t* obs_idx, int64_t n_obs, const double* y, const void* E, int64_t lde,
+                            void* V, void* D, int64_t ldv, hipStream_t s);
+
+// ---------------------------------------------------------------- products
+// G (a x m, FP64, ldg) = A^T B, A: n x a (lda), B: n x m (ldb), split over
+// row chunks with a fixed-order reduction. partial must hold
+// gram_partial_elems(n, a, m) doubles.
+int64_t gram_partial_elems(int64_t n, int a, int m);
+enkf_status launch_gram(enkf_dtype dt, int64_t n, int a, int m, const void* A, int64_t lda, const void* B,
+                        int64_t ldb, double* G, int64_t ldg, double* partial, hipStream_t s);
+
+// X^A = X^B + (X^B - xbar 1^T) (scale G), G = V^T Z (N x N, FP64, ld N),
+// scale = 1/sqrt(N-1); the row means are formed inside.
+enkf_status launch_analysis(enkf_dtype dt, int64_t n_state, int N, const void* XB, int64_t ldx, const double* G,
+                            double scale, void* XA, int64_t ldxa, hipStream_t s);
+
+}  // namespace enkf

@@ -1,0 +1,284 @@
+// Plain iterative Sherman-Morrison sweeps (Section 3.1, Steps 1-2), one
+// kernel launch per level, for gfx950.
+//
+// A launch updates m active columns x_q of X (the U columns k+1..N during
+// the factorisation, or every Z column during a solve):
+//     Step 1 (eq. SM-step-1):  x_q = src_q / r
+//     level k (eq. SM-step-2): x_q <- x_q - h_k c_q,  h_k = u_k^{(k-1)} / gamma_k,
+//                              c_q = v_k^T x_q  (reduced by the previous launch)
+// and, fused into the same pass, the products of the NEXT level,
+//     c'_q = v_{k+1}^T x_q(new),
+// so each level reads and writes its active columns exactly once. Each block
+// leaves one partial of c'_q per column (shuffles within a wave, then LDS
+// across waves). Every block of the next launch sums, by itself and in the
+// same fixed order, the partials of the columns it updates: no atomics or
+// cross-block fences (which on a multi-XCD part would write back the L2), and
+// results are bitwise reproducible. During the factorisation the products of
+// the pivot column give gamma_k = 1 + v_k^T u_k^{(k-1)}; block (0,0) stores it
+// and latches a status error if it is not finite or not > 0 (Section 3.3).
+//
+// Layout: column-major, threads own consecutive row chunks of VW elements
+// (16-byte loads), a block owns LV_THREADS*VW*RPT rows of COLS columns.
+#include "enkf_internal.h"
+
+namespace enkf {
+namespace {
+
+constexpr int LV_THREADS = 256;
+constexpr int LV_WAVES = LV_THREADS / kWave;
+constexpr int LV_COLS = 8;
+constexpr int LV_RPT = 2;
+
+template <typename T, int VW> struct VecT;
+template <> struct VecT<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct VecT<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct VecT<double, 1> { typedef double type; };
+template <> struct VecT<float, 1> { typedef float type; };
+
+template <typename T, int VW>
+__device__ __forceinline__ void load_rows(const T* __restrict__ p, int64_t row, int64_t n, T (&v)[VW]) {
+  if (row + VW <= n) {
+    typedef typename VecT<T, VW>::type vt;
+    vt x = *reinterpret_cast<const vt*>(p + row);
+    if constexpr (VW == 1) {
+      v[0] = x;
+    } else {
+#pragma unroll
+      for (int e = 0; e < VW; ++e) v[e] = x[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < VW; ++e) v[e] = (row + e < n) ? p[row + e] : T(0);
+  }
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void store_rows(T* __restrict__ p, int64_t row, int64_t n, const T (&v)[VW]) {
+  if (row + VW <= n) {
+    typedef typename VecT<T, VW>::type vt;
+    vt x;
+    if constexpr (VW == 1) {
+      x = v[0];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VW; ++e) x[e] = v[e];
+    }
+    *reinterpret_cast<vt*>(p + row) = x;
+  } else {
+#pragma unroll
+    for (int e = 0; e < VW; ++e)
+      if (row + e < n) p[row + e] = v[e];
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum of one value per thread over the block, returned to every thread, in a
+// fixed order (shuffle tree per wave, then waves 0..3).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < LV_WAVES; ++w) s += red[w];
+  return s;
+}
+
+template <typename T, int VW, bool STEP1, bool LOOKAHEAD, bool OWN_GAMMA>
+__global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
+  constexpr int COLS = LV_COLS, RPT = LV_RPT;
+  const int64_t n = a.n;
+  const int nb = gridDim.x;
+  const int g = blockIdx.y;
+  const int col0 = g * COLS;
+  const int ncol = min(COLS, a.m - col0);
+  const int64_t row_base = (int64_t)blockIdx.x * ((int64_t)LV_THREADS * VW * RPT);
+  const int t = threadIdx.x;
+  const int lane = t % kWave, wave = t / kWave;
+  T* __restrict__ X = static_cast<T*>(a.X);
+
+  // Products c_q = v_k^T x_q of this block's columns (and of the pivot
+  // column when forming gamma_k), from the previous launch's partials.
+  __shared__ double cq_s[COLS];
+  __shared__ double gam_s;
+  if constexpr (!STEP1) {
+    const int nred = ncol + (OWN_GAMMA ? 1 : 0);
+    for (int c = wave; c < nred; c += LV_WAVES) {
+      const int pc = (c < ncol) ? (col0 + c + a.prev_off) : 0;
+      const double* __restrict__ p = a.prev + (int64_t)pc * nb;
+      double sacc = 0.0;
+      for (int b = lane; b < nb; b += kWave) sacc += p[b];
+      sacc = wave_sum(sacc);
+      if (lane == 0) {
+        if (c < ncol) cq_s[c] = sacc;
+        else gam_s = sacc;
+      }
+    }
+    __syncthreads();
+  }
+
+  // Per-row factors: 1/r_i (Step 1) or h_k[i] = u_k[i] / gamma_k (level).
+  double hrow[RPT][VW];
+  double vn[RPT][VW];
+  double inv_gamma = 0.0;
+  if constexpr (!STEP1) {
+    double gam;
+    if constexpr (OWN_GAMMA) {
+      gam = 1.0 + gam_s;
+      if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
+        *a.gamma_out = gam;
+        if (!(gam > 0.0) || !__builtin_isfinite(gam)) atomicOr(a.status, kStatusNotSpd);
+      }
+    } else {
+      gam = *a.gamma_in;
+    }
+    inv_gamma = 1.0 / gam;
+  }
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int64_t row = row_base + ((int64_t)r * LV_THREADS + t) * VW;
+    if constexpr (STEP1) {
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        double rv = (row + e < n) ? a.r[row + e] : 1.0;
+        if (!(rv > 0.0) || !__builtin_isfinite(rv)) atomicOr(a.status, kStatusNotSpd);
+        hrow[r][e] = 1.0 / rv;
+      }
+    } else {
+      T u[VW];
+      if (row < n) load_rows<T, VW>(static_cast<const T*>(a.uk), row, n, u);
+#pragma unroll
+      for (int e = 0; e < VW; ++e) hrow[r][e] = (row < n) ? (double)u[e] * inv_gamma : 0.0;
+    }
+    if constexpr (LOOKAHEAD) {
+      T v[VW];
+      if (row < n) load_rows<T, VW>(static_cast<const T*>(a.vnext), row, n, v);
+#pragma unroll
+      for (int e = 0; e < VW; ++e) vn[r][e] = (row < n) ? (double)v[e] : 0.0;
+    }
+  }
+
+  // Load every active value of this block first (columns never overlap; the
+  // source of Step 1 may be the destination itself).
+  T xv[COLS][RPT][VW];
+  const T* __restrict__ src = STEP1 ? static_cast<const T*>(a.src) : X;
+  const int64_t lds = STEP1 ? a.lds : a.ldx;
+#pragma unroll
+  for (int c = 0; c < COLS; ++c) {
+    if (c < ncol) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int64_t row = row_base + ((int64_t)r * LV_THREADS + t) * VW;
+        if (row < n) load_rows<T, VW>(src + (int64_t)(col0 + c) * lds, row, n, xv[c][r]);
+      }
+    }
+  }
+
+  double acc[COLS];
+#pragma unroll
+  for (int c = 0; c < COLS; ++c) {
+    acc[c] = 0.0;
+    if (c < ncol) {
+      double cq = 0.0;
+      if constexpr (!STEP1) cq = cq_s[c];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int64_t row = row_base + ((int64_t)r * LV_THREADS + t) * VW;
+        if (row < n) {
+#pragma unroll
+          for (int e = 0; e < VW; ++e) {
+            double x = (double)xv[c][r][e];
+            x = STEP1 ? x * hrow[r][e] : x - hrow[r][e] * cq;
+            xv[c][r][e] = (T)x;
+            if constexpr (LOOKAHEAD) acc[c] += vn[r][e] * (double)xv[c][r][e];
+          }
+          store_rows<T, VW>(X + (int64_t)(col0 + c) * a.ldx, row, n, xv[c][r]);
+        }
+      }
+    }
+  }
+  if constexpr (!LOOKAHEAD) return;
+
+  // One partial per column for this block.
+  __shared__ double red[LV_WAVES][COLS];
+#pragma unroll
+  for (int c = 0; c < COLS; ++c) {
+    const double v = wave_sum(acc[c]);
+    if (lane == 0) red[wave][c] = v;
+  }
+  __syncthreads();
+  if (t < ncol) {
+    double sacc = 0.0;
+#pragma unroll
+    for (int w = 0; w < LV_WAVES; ++w) sacc += red[w][t];
+    a.part_out[(int64_t)(col0 + t) * nb + blockIdx.x] = sacc;
+  }
+}
+
+// gamma = 1 + (sum of one partial column), summed exactly as the level
+// kernels sum it (lane-strided, then the shuffle tree).
+__global__ __launch_bounds__(kWave) void gamma_kernel(const double* __restrict__ part, int nb, int col,
+                                                      double* __restrict__ gamma_out, unsigned* status) {
+  const double* p = part + (int64_t)col * nb;
+  double sacc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kWave) sacc += p[b];
+  sacc = wave_sum(sacc);
+  if (threadIdx.x == 0) {
+    const double gam = 1.0 + sacc;
+    *gamma_out = gam;
+    if (!(gam > 0.0) || !__builtin_isfinite(gam)) atomicOr(status, kStatusNotSpd);
+  }
+}
+
+template <typename T, int VW>
+enkf_status launch_t(const LevelArgs& a, hipStream_t s) {
+  if (a.m <= 0) return ENKF_SUCCESS;
+  const int64_t rows_per_block = (int64_t)LV_THREADS * VW * LV_RPT;
+  const int64_t nb = (a.n + rows_per_block - 1) / rows_per_block;
+  const int ng = (a.m + LV_COLS - 1) / LV_COLS;
+  if (nb > 0x7fffffff || ng > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "level sweep: problem too large for grid");
+  dim3 grid((unsigned)nb, (unsigned)ng);
+  const bool step1 = a.src != nullptr, look = a.vnext != nullptr, own = a.gamma_out != nullptr;
+  if (step1) {
+    if (look) level_kernel<T, VW, true, true, false><<<grid, LV_THREADS, 0, s>>>(a);
+    else level_kernel<T, VW, true, false, false><<<grid, LV_THREADS, 0, s>>>(a);
+  } else if (own) {
+    if (look) level_kernel<T, VW, false, true, true><<<grid, LV_THREADS, 0, s>>>(a);
+    else level_kernel<T, VW, false, false, true><<<grid, LV_THREADS, 0, s>>>(a);
+  } else {
+    if (look) level_kernel<T, VW, false, true, false><<<grid, LV_THREADS, 0, s>>>(a);
+    else level_kernel<T, VW, false, false, false><<<grid, LV_THREADS, 0, s>>>(a);
+  }
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
+}  // namespace
+
+int level_vw(enkf_dtype dt) { return dt == ENKF_F64 ? 2 : 4; }
+
+int level_row_blocks(enkf_dtype, int vw, int64_t n) {
+  const int64_t rpb = (int64_t)LV_THREADS * vw * LV_RPT;
+  return (int)((n + rpb - 1) / rpb);
+}
+
+enkf_status launch_level(enkf_dtype dt, const LevelArgs& a, hipStream_t s) {
+  if (dt == ENKF_F64) return a.vw == 2 ? launch_t<double, 2>(a, s) : launch_t<double, 1>(a, s);
+  return a.vw == 4 ? launch_t<float, 4>(a, s) : launch_t<float, 1>(a, s);
+}
+
+enkf_status launch_gamma_from_partials(const double* part, int nb, int col, double* gamma_out, unsigned* status,
+                                       hipStream_t s) {
+  gamma_kernel<<<1, kWave, 0, s>>>(part, nb, col, gamma_out, status);
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
+}  // namespace enkf

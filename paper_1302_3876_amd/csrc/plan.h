@@ -1,0 +1,54 @@
+// The plan behind enkf_sm_plan: borrowed inputs, owned workspace, and the
+// launch sequences of the factorisation, solve and analysis.
+#pragma once
+
+#include "enkf_internal.h"
+
+namespace enkf {
+
+size_t dtype_size(enkf_dtype d);
+enkf_status validate_desc(const enkf_sm_desc* d);
+
+struct Plan {
+  enkf_sm_desc desc{};
+  int max_nrhs = 0;
+  hipStream_t stream = nullptr;
+  const double* r = nullptr;
+  const void* V = nullptr;
+  int64_t ldv = 0;
+  size_t es = 8;
+
+  // workspace (one allocation, carved into the pieces below)
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* U = nullptr;            // plain factor: column k = u_k^{(k-1)}
+  int64_t ldu = 0;
+  double* gamma = nullptr;      // N pivots
+  double* part[2] = {nullptr, nullptr};  // level sweeps: per-block partial products, alternating
+  unsigned* status = nullptr;   // device status word
+  double* G = nullptr;          // N x N products V^T Z
+  double* gram_partial = nullptr;
+  int32_t* perm = nullptr;      // pivoting: V column of each level (device)
+  std::vector<int32_t> perm_h;  // host copy of perm after a pivoted factorisation
+
+  Timing timing;
+  enkf_sm_info last{};
+
+  enkf_status create(const enkf_sm_desc& d, const double* r, const void* V, int64_t ldv, hipStream_t s);
+  enkf_status factor();
+  enkf_status solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, enkf_sm_info* info);
+  enkf_status analysis(int64_t n_state, const void* XB, int64_t ldx, const void* Z, int64_t ldz, void* XA,
+                       int64_t ldxa);
+  enkf_status get_info(enkf_sm_info* info);
+  enkf_status get_pivots(double* gamma_host, int32_t* perm_host);
+  enkf_status read_status(unsigned* st);
+  enkf_status clear_status();
+  ~Plan();
+
+ private:
+  enkf_status factor_plain();
+  enkf_status solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
+  const void* vcol(int k) const;  // V column used at level k
+};
+
+}  // namespace enkf

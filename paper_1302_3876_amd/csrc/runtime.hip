@@ -1,0 +1,244 @@
+// C ABI entry points: argument validation on the host, plan and workspace,
+// launch sequencing on the caller's stream, device status word, timing.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "enkf_internal.h"
+#include "plan.h"
+
+namespace enkf {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+enkf_status fail(enkf_status s, const std::string& msg) {
+  g_last_error = std::string(status_name(s)) + ": " + msg;
+  return s;
+}
+
+const char* status_name(enkf_status s) {
+  switch (s) {
+    case ENKF_SUCCESS: return "success";
+    case ENKF_ERR_INVALID_ARG: return "invalid argument";
+    case ENKF_ERR_NOT_SPD: return "not positive definite";
+    case ENKF_ERR_NO_CONVERGENCE: return "refinement did not converge";
+    case ENKF_ERR_HIP: return "HIP runtime error";
+    case ENKF_ERR_OUT_OF_MEMORY: return "out of memory";
+    case ENKF_ERR_NOT_SUPPORTED: return "not supported";
+  }
+  return "unknown status";
+}
+
+// ------------------------------------------------------------------ timing
+hipEvent_t Timing::get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Timing::begin(hipStream_t s, int, double, double, hipEvent_t* a) {
+  *a = get_event();
+  if (*a) (void)hipEventRecord(*a, s);
+}
+
+void Timing::end(hipStream_t s, hipEvent_t a, int cls, double by, double fl) {
+  hipEvent_t b = get_event();
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  pending.push_back({cls, a, b, by, fl});
+}
+
+hipError_t Timing::harvest() {
+  for (auto& r : pending) {
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return e;
+    float ms_ = 0.f;
+    e = hipEventElapsedTime(&ms_, r.a, r.b);
+    if (e != hipSuccess) return e;
+    ms[r.cls] += ms_;
+    bytes[r.cls] += r.bytes;
+    flops[r.cls] += r.flops;
+    launches[r.cls] += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+  return hipSuccess;
+}
+
+void Timing::reset() {
+  for (int i = 0; i < KC_COUNT; ++i) { ms[i] = bytes[i] = flops[i] = 0.0; launches[i] = 0; }
+}
+
+Timing::~Timing() {
+  for (auto& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+size_t dtype_size(enkf_dtype d) { return d == ENKF_F64 ? 8 : 4; }
+
+static bool math_matches_plain(const enkf_sm_desc& d) {
+  return (d.dtype == ENKF_F64 && d.math == ENKF_MATH_F64) || (d.dtype == ENKF_F32 && d.math == ENKF_MATH_F32);
+}
+
+enkf_status validate_desc(const enkf_sm_desc* d) {
+  if (!d) return fail(ENKF_ERR_INVALID_ARG, "desc is NULL");
+  if (d->n_obs < 1) return fail(ENKF_ERR_INVALID_ARG, "n_obs must be >= 1");
+  if (d->n_ens < 1) return fail(ENKF_ERR_INVALID_ARG, "n_ens must be >= 1");
+  if (d->dtype != ENKF_F64 && d->dtype != ENKF_F32) return fail(ENKF_ERR_INVALID_ARG, "unknown dtype");
+  if (d->algo != ENKF_SM_PLAIN && d->algo != ENKF_SM_BLOCKED) return fail(ENKF_ERR_INVALID_ARG, "unknown algo");
+  if (d->math < ENKF_MATH_F64 || d->math > ENKF_MATH_F16X2) return fail(ENKF_ERR_INVALID_ARG, "unknown math");
+  if (d->flags & ~ENKF_FLAG_PIVOT) return fail(ENKF_ERR_INVALID_ARG, "unknown flag bits");
+  if (d->max_nrhs < 0) return fail(ENKF_ERR_INVALID_ARG, "max_nrhs must be >= 0");
+  if (d->refine_max_iter < 0) return fail(ENKF_ERR_INVALID_ARG, "refine_max_iter must be >= 0");
+  if (!(d->refine_tol >= 0.0)) return fail(ENKF_ERR_INVALID_ARG, "refine_tol must be >= 0");
+  if (d->algo == ENKF_SM_PLAIN) {
+    if (!math_matches_plain(*d))
+      return fail(ENKF_ERR_INVALID_ARG, "plain algorithm: math must equal the storage type (F64/F64 or F32/F32)");
+    if (d->block != 0 && d->block != 1) return fail(ENKF_ERR_INVALID_ARG, "plain algorithm: block must be 0 or 1");
+  } else {
+    if (d->block < 0 || d->block > d->n_ens) return fail(ENKF_ERR_INVALID_ARG, "block must be in [0, n_ens]");
+    if (d->flags & ENKF_FLAG_PIVOT) return fail(ENKF_ERR_NOT_SUPPORTED, "pivoting is available for the plain algorithm");
+    if (d->dtype == ENKF_F32 && d->math == ENKF_MATH_F64)
+      return fail(ENKF_ERR_INVALID_ARG, "math F64 needs F64 storage");
+  }
+  return ENKF_SUCCESS;
+}
+
+}  // namespace enkf
+
+using namespace enkf;
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+enkf_status enkf_sm_validate_desc(const enkf_sm_desc* desc) { return validate_desc(desc); }
+
+const char* enkf_status_string(enkf_status s) { return status_name(s); }
+
+const char* enkf_last_error_message(void) { return g_last_error.c_str(); }
+
+enkf_status enkf_build_vd(int64_t n_state, int32_t n_ens, enkf_dtype dtype, const void* XB, int64_t ldx,
+                          const int64_t* obs_idx, int64_t n_obs, const double* y, const void* E, int64_t lde, void* V,
+                          void* D, int64_t ldv, void* stream) {
+  if (n_state < 1 || n_obs < 1) return fail(ENKF_ERR_INVALID_ARG, "build_vd: n_state and n_obs must be >= 1");
+  if (n_ens < 2) return fail(ENKF_ERR_INVALID_ARG, "build_vd: n_ens must be >= 2 (S divides by sqrt(N-1))");
+  if (dtype != ENKF_F64 && dtype != ENKF_F32) return fail(ENKF_ERR_INVALID_ARG, "build_vd: unknown dtype");
+  if (ldx < n_state || lde < n_obs || ldv < n_obs) return fail(ENKF_ERR_INVALID_ARG, "build_vd: leading dimension too small");
+  if (!XB || !obs_idx || !y || !E || !V || !D) return fail(ENKF_ERR_INVALID_ARG, "build_vd: NULL pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return launch_build_vd(dtype, n_state, n_ens, XB, ldx, obs_idx, n_obs, y, E, lde, V, D, ldv, s);
+}
+
+enkf_status enkf_sm_init(enkf_sm_plan* out, const enkf_sm_desc* desc, const double* r, const void* V, int64_t ldv,
+                         void* stream) {
+  if (!out) return fail(ENKF_ERR_INVALID_ARG, "init: out is NULL");
+  *out = nullptr;
+  enkf_status st = validate_desc(desc);
+  if (st != ENKF_SUCCESS) return st;
+  if (!r || !V) return fail(ENKF_ERR_INVALID_ARG, "init: r or V is NULL");
+  if (ldv < desc->n_obs) return fail(ENKF_ERR_INVALID_ARG, "init: ldv < n_obs");
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return fail(ENKF_ERR_OUT_OF_MEMORY, "init: plan");
+  st = p->create(*desc, r, V, ldv, static_cast<hipStream_t>(stream));
+  if (st != ENKF_SUCCESS) {
+    delete p;
+    return st;
+  }
+  st = p->factor();
+  if (st != ENKF_SUCCESS) {
+    delete p;
+    return st;
+  }
+  *out = reinterpret_cast<enkf_sm_plan>(p);
+  return ENKF_SUCCESS;
+}
+
+enkf_status enkf_sm_refactor(enkf_sm_plan plan, const double* r, const void* V, int64_t ldv) {
+  if (!plan) return fail(ENKF_ERR_INVALID_ARG, "refactor: plan is NULL");
+  if (!r || !V) return fail(ENKF_ERR_INVALID_ARG, "refactor: r or V is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (ldv < p->desc.n_obs) return fail(ENKF_ERR_INVALID_ARG, "refactor: ldv < n_obs");
+  p->r = r;
+  p->V = V;
+  p->ldv = ldv;
+  enkf_status st = p->clear_status();
+  if (st != ENKF_SUCCESS) return st;
+  return p->factor();
+}
+
+enkf_status enkf_sm_solve(enkf_sm_plan plan, int32_t nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz,
+                          enkf_sm_info* info) {
+  if (!plan) return fail(ENKF_ERR_INVALID_ARG, "solve: plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (nrhs < 0 || nrhs > p->max_nrhs) return fail(ENKF_ERR_INVALID_ARG, "solve: nrhs outside [0, max_nrhs]");
+  if (nrhs > 0) {
+    if (!D || !Z) return fail(ENKF_ERR_INVALID_ARG, "solve: D or Z is NULL");
+    if (ldd < p->desc.n_obs || ldz < p->desc.n_obs) return fail(ENKF_ERR_INVALID_ARG, "solve: leading dimension < n_obs");
+    if (D == Z && ldd != ldz) return fail(ENKF_ERR_INVALID_ARG, "solve: Z aliases D with a different leading dimension");
+  }
+  return p->solve(nrhs, D, ldd, Z, ldz, info);
+}
+
+enkf_status enkf_analysis(enkf_sm_plan plan, int64_t n_state, const void* XB, int64_t ldx, const void* Z, int64_t ldz,
+                          void* XA, int64_t ldxa) {
+  if (!plan) return fail(ENKF_ERR_INVALID_ARG, "analysis: plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (n_state < 1) return fail(ENKF_ERR_INVALID_ARG, "analysis: n_state must be >= 1");
+  if (p->desc.n_ens < 2) return fail(ENKF_ERR_INVALID_ARG, "analysis: n_ens must be >= 2");
+  if (!XB || !Z || !XA) return fail(ENKF_ERR_INVALID_ARG, "analysis: NULL pointer");
+  if (ldx < n_state || ldxa < n_state || ldz < p->desc.n_obs)
+    return fail(ENKF_ERR_INVALID_ARG, "analysis: leading dimension too small");
+  const size_t es = dtype_size(p->desc.dtype);
+  const uintptr_t xb0 = (uintptr_t)XB, xb1 = xb0 + ((size_t)ldx * (p->desc.n_ens - 1) + n_state) * es;
+  const uintptr_t xa0 = (uintptr_t)XA, xa1 = xa0 + ((size_t)ldxa * (p->desc.n_ens - 1) + n_state) * es;
+  if (xa0 < xb1 && xb0 < xa1) return fail(ENKF_ERR_INVALID_ARG, "analysis: XA overlaps XB");
+  return p->analysis(n_state, XB, ldx, Z, ldz, XA, ldxa);
+}
+
+enkf_status enkf_sm_get_info(enkf_sm_plan plan, enkf_sm_info* info) {
+  if (!plan || !info) return fail(ENKF_ERR_INVALID_ARG, "get_info: NULL argument");
+  return reinterpret_cast<Plan*>(plan)->get_info(info);
+}
+
+enkf_status enkf_sm_get_pivots(enkf_sm_plan plan, double* gamma_host, int32_t* perm_host) {
+  if (!plan || !gamma_host) return fail(ENKF_ERR_INVALID_ARG, "get_pivots: NULL argument");
+  return reinterpret_cast<Plan*>(plan)->get_pivots(gamma_host, perm_host);
+}
+
+void enkf_sm_destroy(enkf_sm_plan plan) {
+  if (!plan) return;
+  delete reinterpret_cast<Plan*>(plan);
+}
+
+enkf_status enkf_sm_set_timing(enkf_sm_plan plan, int32_t enable) {
+  if (!plan) return fail(ENKF_ERR_INVALID_ARG, "set_timing: plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (p->timing.harvest() != hipSuccess) return fail(ENKF_ERR_HIP, "set_timing: event harvest failed");
+  p->timing.reset();
+  p->timing.enabled = enable != 0;
+  return ENKF_SUCCESS;
+}
+
+enkf_status enkf_sm_get_timing(enkf_sm_plan plan, int32_t kernel_class, double* total_ms, int64_t* launches,
+                               double* alg_bytes, double* alg_flops) {
+  if (!plan || kernel_class < 0 || kernel_class >= KC_COUNT) return fail(ENKF_ERR_INVALID_ARG, "get_timing: bad argument");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (p->timing.harvest() != hipSuccess) return fail(ENKF_ERR_HIP, "get_timing: event harvest failed");
+  if (total_ms) *total_ms = p->timing.ms[kernel_class];
+  if (launches) *launches = p->timing.launches[kernel_class];
+  if (alg_bytes) *alg_bytes = p->timing.bytes[kernel_class];
+  if (alg_flops) *alg_flops = p->timing.flops[kernel_class];
+  return ENKF_SUCCESS;
+}
+
+}  // extern "C"

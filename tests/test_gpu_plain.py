@@ -1,0 +1,157 @@
+"""Parity of the plain HIP path (build, level sweeps, analysis) with the FP64
+oracle, on the same seeded inputs, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, fp64_gate, host, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _pk():
+    import paper_1302_3876_amd as pk
+    return pk
+
+
+@pytest.mark.parametrize("n,N,nrhs", [(1, 1, 1), (5, 3, 2), (7, 1, 3), (1000, 17, 17), (4099, 33, 5),
+                                      (16384, 96, 96), (70001, 40, 40), (3, 50, 50)])
+def test_solve_fp64_matches_oracle(n, N, nrhs):
+    import torch
+    print(f"solve fp64 n={n} N={N} nrhs={nrhs}", flush=True)
+    r, V, D = synth.small_vd(n, N, seed=1000 + n + N, nrhs=nrhs)
+    plan = _pk().Plan(dev(r), dev(V), max_nrhs=nrhs)
+    Z, info = plan.solve(dev(D), info=True)
+    torch.cuda.synchronize()
+    ref = oracle.sm_solve(r, V, D)
+    fp64_gate(r, V, D, host(Z), ref["Z"])
+    g, _ = plan.pivots()
+    assert np.allclose(g, ref["gamma"], rtol=1e-12, atol=0)
+    assert info["device_status"] == 0
+
+
+@pytest.mark.parametrize("n,N", [(4099, 33), (65536, 64)])
+def test_solve_fp32_matches_oracle(n, N):
+    import torch
+    print(f"solve fp32 n={n} N={N}", flush=True)
+    r, V, D = synth.small_vd(n, N, seed=2000 + n, r_range=(0.005, 0.02), v_scale=0.3)
+    plan = _pk().Plan(dev(r), dev(V, torch.float32))
+    Z = plan.solve(dev(D, torch.float32))
+    torch.cuda.synchronize()
+    ref = oracle.sm_solve(r, V.astype(np.float32).astype(np.float64), D.astype(np.float32).astype(np.float64))
+    # FP32 storage: every level rounds the updated columns to FP32 (unit
+    # roundoff 6e-8); the forward error stays within a few hundred units times
+    # the growth in the pivots.
+    assert rel(host(Z), ref["Z"]) < 1e-4
+
+
+def test_unaligned_leading_dimension_and_alias():
+    import torch
+    pk = _pk()
+    n, N = 1001, 9
+    r, V, D = synth.small_vd(n, N, seed=5)
+    Vp = pk.colmajor(n + 1, N)[:n]           # ld = n + 1 (odd): scalar path
+    Vp.copy_(torch.as_tensor(V))
+    Dp = pk.colmajor(n + 3, N)[:n]
+    Dp.copy_(torch.as_tensor(D))
+    plan = pk.Plan(dev(r), Vp)
+    Z = plan.solve(Dp, Dp)                    # in place: Z aliases D
+    torch.cuda.synchronize()
+    fp64_gate(r, V, D, host(Z), oracle.sm_solve(r, V, D)["Z"])
+
+
+def test_zero_rhs_and_zero_column():
+    import torch
+    pk = _pk()
+    n, N = 300, 6
+    r, V, D = synth.small_vd(n, N, seed=9)
+    V[:, 2] = 0.0
+    plan = pk.Plan(dev(r), dev(V))
+    empty = pk.colmajor(n, 0)
+    plan.solve(empty, empty)
+    Z = plan.solve(dev(D))
+    torch.cuda.synchronize()
+    g, _ = plan.pivots()
+    assert g[2] == 1.0
+    fp64_gate(r, V, D, host(Z), oracle.sm_solve(r, V, D)["Z"])
+
+
+def test_nonpositive_r_is_reported():
+    pk = _pk()
+    n, N = 200, 4
+    r, V, D = synth.small_vd(n, N, seed=3)
+    r[17] = 0.0
+    plan = pk.Plan(dev(r), dev(V))
+    with pytest.raises(pk.EnkfError) as e:
+        plan.info()
+    assert e.value.code == 2
+
+
+def test_bitwise_reproducible():
+    import torch
+    pk = _pk()
+    r, V, D = synth.small_vd(50000, 24, seed=12)
+    a = host(pk.Plan(dev(r), dev(V)).solve(dev(D)))
+    b = host(pk.Plan(dev(r), dev(V)).solve(dev(D)))
+    torch.cuda.synchronize()
+    assert np.array_equal(a, b)
+
+
+def _full_path(w, dtype):
+    import torch
+    pk = _pk()
+    XB = dev(w.XB, dtype)
+    E = dev(w.E, dtype)
+    V, D = pk.enkf_build_vd(XB, dev(w.obs_idx), dev(w.y), E)
+    plan = pk.Plan(dev(w.r), V)
+    Z = plan.solve(D)
+    XA = plan.analysis(XB, Z)
+    torch.cuda.synchronize()
+    return host(V), host(D), host(Z), host(XA), plan
+
+
+def test_c1_full_path_fp64():
+    w = synth.c1()
+    V, D, Z, XA, plan = _full_path(w, None)
+    Vo, Do = oracle.build_vd(w.XB, w.obs_idx, w.y, w.E)
+    assert np.allclose(V, Vo, rtol=1e-14, atol=1e-16)
+    assert np.allclose(D, Do, rtol=1e-14, atol=1e-16)
+    Zo = oracle.sm_solve(w.r, Vo, Do)["Z"]
+    fp64_gate(w.r, Vo, Do, Z, Zo)
+    XAo = oracle.analysis(w.XB, Vo, Zo)
+    assert rel(XA - w.XB, XAo - w.XB) < 1e-11
+
+
+@pytest.mark.slow
+def test_c2_full_path_fp64_full_size():
+    print("c2 full size fp64", flush=True)
+    w = synth.c2()
+    V, D, Z, XA, plan = _full_path(w, None)
+    Vo, Do = oracle.build_vd(w.XB, w.obs_idx, w.y, w.E)
+    assert rel(V, Vo) < 1e-14 and rel(D, Do) < 1e-15
+    Zo = oracle.sm_solve(w.r, Vo, Do)["Z"]
+    g = fp64_gate(w.r, Vo, Do, Z, Zo)
+    print(g, flush=True)
+    XAo = oracle.analysis(w.XB, Vo, Zo)
+    assert rel(XA - w.XB, XAo - w.XB) < 1e-8
+    # every element of the increment, not only the norm
+    inc, inco = XA - w.XB, XAo - w.XB
+    assert np.max(np.abs(inc - inco)) <= 1e-8 * np.max(np.abs(inco))
+
+
+@pytest.mark.slow
+def test_c2_full_path_fp32_full_size():
+    import torch
+    print("c2 full size fp32", flush=True)
+    w = synth.c2()
+    V, D, Z, XA, plan = _full_path(w, torch.float32)
+    XB32 = w.XB.astype(np.float32).astype(np.float64)
+    E32 = w.E.astype(np.float32).astype(np.float64)
+    Vo, Do = oracle.build_vd(XB32, w.obs_idx, w.y, E32)
+    Zo = oracle.sm_solve(w.r, Vo, Do)["Z"]
+    rz = rel(Z, Zo)
+    XAo = oracle.analysis(XB32, Vo, Zo)
+    ra = rel(XA - XB32, XAo - XB32)
+    print({"z_rel": rz, "increment_rel": ra}, flush=True)
+    assert rz < 1e-2 and ra < 1e-2
