@@ -27,7 +27,8 @@ enum KernelClass : int {
   KC_PANEL_UPDATE = 5, // blocked: X -= U_K Q (+ look-ahead products)
   KC_PANEL_FACTOR = 6, // blocked: b x b LDL^T and solves
   KC_RESIDUAL = 7,     // FP64 residual of the refinement
-  KC_COUNT = 8
+  KC_STEP1 = 8,        // blocked: Step 1 row scaling
+  KC_COUNT = 9
 };
 
 void set_error(const std::string& msg);
@@ -103,18 +104,5 @@ int level_vw(enkf_dtype dt);
 enkf_status launch_build_vd(enkf_dtype dt, int64_t n_state, int n_ens, const void* XB, int64_t ldx,
                             const int64_t* obs_idx, int64_t n_obs, const double* y, const void* E, int64_t lde,
                             void* V, void* D, int64_t ldv, hipStream_t s);
-
-// ---------------------------------------------------------------- products
-// G (a x m, FP64, ldg) = A^T B, A: n x a (lda), B: n x m (ldb), split over
-// row chunks with a fixed-order reduction. partial must hold
-// gram_partial_elems(n, a, m) doubles.
-int64_t gram_partial_elems(int64_t n, int a, int m);
-enkf_status launch_gram(enkf_dtype dt, int64_t n, int a, int m, const void* A, int64_t lda, const void* B,
-                        int64_t ldb, double* G, int64_t ldg, double* partial, hipStream_t s);
-
-// X^A = X^B + (X^B - xbar 1^T) (scale G), G = V^T Z (N x N, FP64, ld N),
-// scale = 1/sqrt(N-1); the row means are formed inside.
-enkf_status launch_analysis(enkf_dtype dt, int64_t n_state, int N, const void* XB, int64_t ldx, const double* G,
-                            double scale, void* XA, int64_t ldxa, hipStream_t s);
 
 }  // namespace enkf

@@ -1,0 +1,33 @@
+// Launchers of the matrix-core products (gemm_mfma.hip).
+#pragma once
+
+#include "enkf_internal.h"
+
+namespace enkf {
+
+enum NnMode : int { NN_UPDATE = 0, NN_ANALYSIS = 1, NN_RESIDUAL = 2 };
+
+struct NnArgs {
+  int64_t n;            // rows
+  int K;                // inner dimension (columns of A, rows of Bm)
+  int m;                // output columns
+  const void* A; int64_t lda;        // n x K, storage type
+  const double* Bm; int64_t ldb;     // K x m, FP64
+  double scale;                      // Bm is multiplied by scale (ANALYSIS); 1 otherwise
+  const void* Cin; int64_t ldc;      // UPDATE: X; ANALYSIS: XB; RESIDUAL: Z
+  void* Cout; int64_t ldo;           // UPDATE: X (same as Cin); ANALYSIS: XA; RESIDUAL: rho
+  const void* Din; int64_t ldd;      // RESIDUAL: D
+  const double* r;                   // RESIDUAL: diag(R)
+  int64_t n_row_tiles;               // set by the launcher
+  int n_col_tiles;                   // set by the launcher
+};
+
+// G (a x m, FP64, ldg) = A^T B with split-K partials (partial must hold
+// tn_partial_elems doubles); matrix cores in the storage precision.
+int64_t tn_partial_elems(int64_t n, int a, int m);
+enkf_status launch_tn(enkf_dtype dt, int64_t n, int a, int m, const void* A, int64_t lda, const void* B, int64_t ldb,
+                      double* G, int64_t ldg, double* partial, hipStream_t s);
+
+enkf_status launch_nn(enkf_dtype dt, int mode, NnArgs p, hipStream_t s);
+
+}  // namespace enkf

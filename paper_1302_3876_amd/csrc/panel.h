@@ -1,0 +1,29 @@
+// Launchers of the blocked-solve helper kernels (panel_kernels.hip).
+#pragma once
+
+#include "enkf_internal.h"
+
+namespace enkf {
+
+constexpr int kMaxPanel = 128;   // panel widths up to 128 (two packed b x b triangles fit in LDS)
+
+// Y = R^{-1} X row by row (Step 1); latches NOT_SPD for r_i <= 0 or non-finite.
+enkf_status launch_scale_rows(enkf_dtype dt, int64_t n, int m, const void* X, int64_t ldx, const double* r, void* Y,
+                              int64_t ldy, unsigned* status, hipStream_t s);
+// M = I + sym(P[:, :b]) = L D L^T; gamma_out[0..b) = D; Minv = M^{-1} (b x b, ld b).
+enkf_status launch_panel_factor(int b, const double* P, int64_t ldp, double* gamma_out, double* Minv, unsigned* status,
+                                hipStream_t s);
+// Q (b x m, ld b) = Minv Pr, Pr b x m with leading dimension ldp.
+enkf_status launch_small_gemm(int b, int m, const double* Minv, const double* Pr, int64_t ldp, double* Q,
+                              hipStream_t s);
+
+// FP64 -> FP32 copy; FP32 -> FP64 copy or accumulation (mixed precision).
+enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float* Y, int64_t ldy, hipStream_t s);
+enkf_status launch_widen(int64_t n, int m, const float* W, int64_t ldw, double* Z, int64_t ldz, bool accumulate,
+                         hipStream_t s);
+// out[0] = ||X||_F^2, out[1] = ||Y||_F^2 (fixed-order two-stage sums).
+int norm_partial_elems();
+enkf_status launch_sumsq2(int64_t n, int m, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* part,
+                          double* out, hipStream_t s);
+
+}  // namespace enkf

@@ -1,0 +1,221 @@
+// Small kernels of the blocked solve (gfx950):
+//  - Step 1 as a row scaling, Y = R^{-1} X (eq. SM-step-1);
+//  - the FP64 factorisation of one panel: with P = V_K^T [U_K, X] (b rows),
+//    M = I + V_K^T U_K (symmetrised) is factored M = L D L^T in LDS; the
+//    pivots D are the gamma_k of the panel's b levels (Section 3.3); the
+//    kernel leaves M^{-1} = L^{-T} D^{-1} L^{-1} for the panel update
+//    X <- X - U_K M^{-1} V_K^T X (eq. SWM with a rank-b term);
+//  - Q = M^{-1} P_X, a b x m product in FP64.
+#include "enkf_internal.h"
+#include "panel.h"
+
+namespace enkf {
+namespace {
+
+__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
+
+template <typename T>
+__global__ __launch_bounds__(256) void scale_rows_kernel(int64_t n, int m, const T* __restrict__ X, int64_t ldx,
+                                                         const double* __restrict__ r, T* __restrict__ Y, int64_t ldy,
+                                                         unsigned* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const double rv = r[i];
+  if (c == 0 && (!(rv > 0.0) || !__builtin_isfinite(rv))) atomicOr(status, kStatusNotSpd);
+  for (int j = c; j < m; j += gridDim.y) Y[i + (int64_t)j * ldy] = (T)((double)X[i + (int64_t)j * ldx] / rv);
+}
+
+// One block. Dynamic LDS: two packed lower triangles of b(b+1)/2 doubles.
+__global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* __restrict__ P, int64_t ldp,
+                                                           double* __restrict__ gamma_out, double* __restrict__ Minv,
+                                                           unsigned* status) {
+  extern __shared__ double sm[];
+  double* Lm = sm;                       // M, then L (strict lower) and D (diagonal)
+  double* Tm = sm + b * (b + 1) / 2;     // L^{-1} (strict lower; unit diagonal implied)
+  const int t = threadIdx.x;
+  for (int i = 0; i < b; ++i)
+    for (int j = t; j <= i; j += 256)
+      Lm[tri(i, j)] = (i == j ? 1.0 : 0.0) + 0.5 * (P[i + (int64_t)j * ldp] + P[j + (int64_t)i * ldp]);
+  __syncthreads();
+  // right-looking LDL^T
+  const int ti = t % 16, tk = t / 16;
+  for (int j = 0; j < b; ++j) {
+    const double d = Lm[tri(j, j)];
+    if (t == 0) {
+      gamma_out[j] = d;
+      if (!(d > 0.0) || !__builtin_isfinite(d)) atomicOr(status, kStatusNotSpd);
+    }
+    const double inv_d = 1.0 / d;
+    for (int i = j + 1 + ti; i < b; i += 16) {
+      const double aij = Lm[tri(i, j)];
+      for (int k = j + 1 + tk; k <= i; k += 16) Lm[tri(i, k)] -= aij * Lm[tri(k, j)] * inv_d;
+    }
+    __syncthreads();
+    for (int i = j + 1 + t; i < b; i += 256) Lm[tri(i, j)] *= inv_d;
+    __syncthreads();
+  }
+  // T = L^{-1}: row i from rows < i
+  for (int i = 1; i < b; ++i) {
+    for (int j = t; j < i; j += 256) {
+      double s = Lm[tri(i, j)];
+      for (int k = j + 1; k < i; ++k) s += Lm[tri(i, k)] * Tm[tri(k, j)];
+      Tm[tri(i, j)] = -s;
+    }
+    __syncthreads();
+  }
+  // M^{-1} = T^T D^{-1} T
+  for (int e = t; e < b * b; e += 256) {
+    const int i = e % b, j = e / b;
+    const int k0 = i > j ? i : j;
+    double s = 0.0;
+    for (int k = k0; k < b; ++k) {
+      const double tki = (k == i) ? 1.0 : Tm[tri(k, i)];
+      const double tkj = (k == j) ? 1.0 : Tm[tri(k, j)];
+      s += tki * tkj / Lm[tri(k, k)];
+    }
+    Minv[i + (int64_t)j * b] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void small_gemm_kernel(int b, int m, const double* __restrict__ Minv,
+                                                         const double* __restrict__ Pr, int64_t ldp,
+                                                         double* __restrict__ Q) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)b * m) return;
+  const int i = (int)(e % b);
+  const int64_t j = e / b;
+  double s = 0.0;
+  for (int k = 0; k < b; ++k) s += Minv[i + (int64_t)k * b] * Pr[k + j * ldp];
+  Q[i + j * b] = s;
+}
+
+__global__ __launch_bounds__(256) void convert_kernel(int64_t n, int m, const double* __restrict__ X, int64_t ldx,
+                                                      float* __restrict__ Y, int64_t ldy) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int j = blockIdx.y; j < m; j += gridDim.y) Y[i + (int64_t)j * ldy] = (float)X[i + (int64_t)j * ldx];
+}
+
+// Z = W (accumulate == 0) or Z += W (accumulate == 1), W in FP32.
+__global__ __launch_bounds__(256) void widen_kernel(int64_t n, int m, const float* __restrict__ W, int64_t ldw,
+                                                    double* __restrict__ Z, int64_t ldz, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int j = blockIdx.y; j < m; j += gridDim.y) {
+    const double w = (double)W[i + (int64_t)j * ldw];
+    double* z = Z + i + (int64_t)j * ldz;
+    *z = accumulate ? *z + w : w;
+  }
+}
+
+constexpr int NORM_BLOCKS = 1024;
+
+// Per-block partial sums of squares of two n x m FP64 matrices, in a fixed
+// order; then one block sums the partials.
+__global__ __launch_bounds__(256) void sumsq_partial_kernel(int64_t n, int m, const double* __restrict__ X, int64_t ldx,
+                                                            const double* __restrict__ Y, int64_t ldy,
+                                                            double* __restrict__ part) {
+  __shared__ double red[2][4];
+  const int64_t total = n * (int64_t)m;
+  double sx = 0.0, sy = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e % n, j = e / n;
+    const double x = X[i + j * ldx], y = Y[i + j * ldy];
+    sx += x * x;
+    sy += y * y;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sx += __shfl_xor(sx, off, 64);
+    sy += __shfl_xor(sy, off, 64);
+  }
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  if (lane == 0) { red[0][w] = sx; red[1][w] = sy; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    part[2 * blockIdx.x + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  }
+}
+
+__global__ __launch_bounds__(64) void sumsq_final_kernel(int nblk, const double* __restrict__ part, double* __restrict__ out) {
+  double sx = 0.0, sy = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) { sx += part[2 * b]; sy += part[2 * b + 1]; }
+  for (int off = 32; off > 0; off >>= 1) {
+    sx += __shfl_xor(sx, off, 64);
+    sy += __shfl_xor(sy, off, 64);
+  }
+  if (threadIdx.x == 0) { out[0] = sx; out[1] = sy; }
+}
+
+}  // namespace
+
+int norm_partial_elems() { return 2 * NORM_BLOCKS; }
+
+enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float* Y, int64_t ldy, hipStream_t s) {
+  if (m <= 0) return ENKF_SUCCESS;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(m < 16 ? m : 16));
+  convert_kernel<<<grid, 256, 0, s>>>(n, m, X, ldx, Y, ldy);
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
+enkf_status launch_widen(int64_t n, int m, const float* W, int64_t ldw, double* Z, int64_t ldz, bool accumulate,
+                         hipStream_t s) {
+  if (m <= 0) return ENKF_SUCCESS;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(m < 16 ? m : 16));
+  widen_kernel<<<grid, 256, 0, s>>>(n, m, W, ldw, Z, ldz, accumulate ? 1 : 0);
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
+enkf_status launch_sumsq2(int64_t n, int m, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* part,
+                          double* out, hipStream_t s) {
+  const int64_t total = n * (int64_t)m;
+  int nblk = (int)((total + 255) / 256);
+  if (nblk > NORM_BLOCKS) nblk = NORM_BLOCKS;
+  if (nblk < 1) nblk = 1;
+  sumsq_partial_kernel<<<nblk, 256, 0, s>>>(n, m, X, ldx, Y, ldy, part);
+  ENKF_HIP_CHECK(hipGetLastError());
+  sumsq_final_kernel<<<1, 64, 0, s>>>(nblk, part, out);
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
+enkf_status launch_scale_rows(enkf_dtype dt, int64_t n, int m, const void* X, int64_t ldx, const double* r, void* Y,
+                              int64_t ldy, unsigned* status, hipStream_t s) {
+  if (m <= 0) return ENKF_SUCCESS;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(m < 16 ? m : 16));
+  if (dt == ENKF_F64)
+    scale_rows_kernel<double><<<grid, 256, 0, s>>>(n, m, (const double*)X, ldx, r, (double*)Y, ldy, status);
+  else
+    scale_rows_kernel<float><<<grid, 256, 0, s>>>(n, m, (const float*)X, ldx, r, (float*)Y, ldy, status);
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
+enkf_status launch_panel_factor(int b, const double* P, int64_t ldp, double* gamma_out, double* Minv, unsigned* status,
+                                hipStream_t s) {
+  if (b < 1 || b > kMaxPanel) return fail(ENKF_ERR_NOT_SUPPORTED, "panel width outside [1, 128]");
+  const size_t lds = sizeof(double) * (size_t)b * (b + 1);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)panel_factor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double) * kMaxPanel * (kMaxPanel + 1)));
+    attr_set = true;
+  }
+  panel_factor_kernel<<<1, 256, lds, s>>>(b, P, ldp, gamma_out, Minv, status);
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
+enkf_status launch_small_gemm(int b, int m, const double* Minv, const double* Pr, int64_t ldp, double* Q,
+                              hipStream_t s) {
+  if (m <= 0) return ENKF_SUCCESS;
+  const int64_t total = (int64_t)b * m;
+  small_gemm_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(b, m, Minv, Pr, ldp, Q);
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
+}  // namespace enkf

@@ -26,8 +26,21 @@ struct Plan {
   double* gamma = nullptr;      // N pivots
   double* part[2] = {nullptr, nullptr};  // level sweeps: per-block partial products, alternating
   unsigned* status = nullptr;   // device status word
-  double* G = nullptr;          // N x N products V^T Z
-  double* gram_partial = nullptr;
+  double* G = nullptr;          // N x N products V^T Z (analysis), N x nrhs (residual)
+  double* tn_part = nullptr;    // split-K partials of the tn products
+  // blocked
+  int block = 0;                // panel width b
+  int npanel = 0;
+  double* Minv = nullptr;       // npanel x (b x b) inverse panel matrices
+  double* Pbuf = nullptr;       // b x (N + max_nrhs) panel products
+  double* Qbuf = nullptr;       // b x max(N, max_nrhs)
+  // mixed precision (math narrower than dtype): FP32 working copies
+  bool mixed = false;
+  enkf_dtype wdt = ENKF_F64;    // working storage type of U, panels, Z-sweeps
+  void* Vw = nullptr;           // FP32 copy of V (mixed)
+  void* Zw = nullptr;           // FP32 correction (mixed), n x max_nrhs
+  double* rho = nullptr;        // FP64 residual (mixed), n x max_nrhs
+  double* norms = nullptr;      // [0] ||rho||^2, [1] ||D||^2 (mixed)
   int32_t* perm = nullptr;      // pivoting: V column of each level (device)
   std::vector<int32_t> perm_h;  // host copy of perm after a pivoted factorisation
 
@@ -48,6 +61,12 @@ struct Plan {
  private:
   enkf_status factor_plain();
   enkf_status solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
+  enkf_status factor_blocked();
+  // Z = (R + V V^T)^{-1} D with the blocked factor, all in the working type.
+  enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
+  enkf_status solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
+  const void* vwork() const { return mixed ? Vw : V; }
+  int64_t ldvw() const { return mixed ? ldu : ldv; }
   const void* vcol(int k) const;  // V column used at level k
 };
 

@@ -1,10 +1,12 @@
 // Plan: workspace layout and the launch sequences of the factorisation,
-// solve and analysis.
+// solve and analysis, for the plain, blocked and mixed-precision forms.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
 
+#include "gemm_mfma.h"
+#include "panel.h"
 #include "plan.h"
 
 namespace enkf {
@@ -13,11 +15,27 @@ namespace {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+bool vec_ok(const void* p, int64_t ld, int vw, size_t es) {
+  return p == nullptr || (((uintptr_t)p % (vw * es)) == 0 && (ld % vw) == 0);
+}
+
+__global__ void clear_words_kernel(unsigned* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0u;
+}
+
+// Byte and flop model of one plain sweep launch over m columns of n rows:
+// read and write the m columns, read u_k and v_{k+1} (Step 1: the source
+// columns and r instead of u_k); flops 4 m n (update + look-ahead product).
+void sweep_model(int64_t n, int m, size_t es, bool step1, bool look, double* by, double* fl) {
+  const double cols = 2.0 * m + (look ? 1.0 : 0.0) + (step1 ? 0.0 : 1.0);
+  *by = cols * (double)n * (double)es + (step1 ? 8.0 * (double)n : 0.0);
+  *fl = (double)n * m * (look ? 4.0 : 2.0);
+}
+
 }  // namespace
 
-const void* Plan::vcol(int k) const {
-  return static_cast<const char*>(V) + (size_t)k * (size_t)ldv * es;
-}
+const void* Plan::vcol(int k) const { return static_cast<const char*>(V) + (size_t)k * (size_t)ldv * es; }
 
 enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_, int64_t ldv_, hipStream_t s) {
   desc = d;
@@ -27,25 +45,57 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   stream = s;
   es = dtype_size(d.dtype);
   max_nrhs = d.max_nrhs > 0 ? d.max_nrhs : d.n_ens;
-  if (d.algo != ENKF_SM_PLAIN) return fail(ENKF_ERR_NOT_SUPPORTED, "init: only the plain algorithm is available");
   if (d.flags & ENKF_FLAG_PIVOT) return fail(ENKF_ERR_NOT_SUPPORTED, "init: pivoting is not available yet");
-
   const int64_t n = d.n_obs;
   const int N = d.n_ens;
   const int mcols = std::max(N, max_nrhs);
+  const bool blocked = d.algo == ENKF_SM_BLOCKED;
+  mixed = blocked && d.dtype == ENKF_F64 && d.math != ENKF_MATH_F64;
+  wdt = mixed ? ENKF_F32 : d.dtype;
+  const size_t wes = dtype_size(wdt);
+  if (blocked) {
+    block = d.block > 0 ? d.block : std::min(N, kMaxPanel);
+    if (block > kMaxPanel) return fail(ENKF_ERR_NOT_SUPPORTED, "init: panel width above 128");
+    npanel = (N + block - 1) / block;
+    if (d.math != ENKF_MATH_F64 && d.math != ENKF_MATH_F32)
+      return fail(ENKF_ERR_NOT_SUPPORTED, "init: this math type is not available yet");
+  }
   ldu = (int64_t)align_up((size_t)n, 64);
 
-  // carve the workspace
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  const size_t oU = take((size_t)ldu * N * es);
+  const size_t oU = take((size_t)ldu * N * wes);
   const size_t oGamma = take(sizeof(double) * N);
-  const size_t part_elems = (size_t)level_row_blocks(d.dtype, 1, n) * mcols;
-  const size_t oP0 = take(sizeof(double) * part_elems);
-  const size_t oP1 = take(sizeof(double) * part_elems);
   const size_t oStat = take(sizeof(unsigned) * 4);
-  const size_t oG = take(sizeof(double) * (size_t)N * N);
-  const size_t oGP = take(sizeof(double) * (size_t)gram_partial_elems(n, N, N));
+  const size_t oG = take(sizeof(double) * (size_t)N * mcols);
+  // split-K partials: the largest over every (a, m) product this plan runs
+  int64_t tnp = tn_partial_elems(n, N, N);   // analysis V^T Z
+  if (blocked) {
+    for (int p = 0; p < npanel; ++p) {
+      const int k0 = p * block, bl = std::min(block, N - k0);
+      tnp = std::max(tnp, tn_partial_elems(n, bl, N - k0));
+      for (int m = 1; m <= max_nrhs; ++m) tnp = std::max(tnp, tn_partial_elems(n, bl, m));
+    }
+  }
+  if (mixed)
+    for (int m = 1; m <= max_nrhs; ++m) tnp = std::max(tnp, tn_partial_elems(n, N, m));
+  const size_t oTn = take(sizeof(double) * (size_t)tnp);
+  size_t oP0 = 0, oP1 = 0, oMinv = 0, oPbuf = 0, oQbuf = 0, oVw = 0, oZw = 0, oRho = 0, oNorm = 0;
+  if (!blocked) {
+    const size_t part_elems = (size_t)level_row_blocks(d.dtype, 1, n) * mcols;
+    oP0 = take(sizeof(double) * part_elems);
+    oP1 = take(sizeof(double) * part_elems);
+  } else {
+    oMinv = take(sizeof(double) * (size_t)npanel * block * block);
+    oPbuf = take(sizeof(double) * (size_t)block * (N + mcols));
+    oQbuf = take(sizeof(double) * (size_t)block * mcols);
+  }
+  if (mixed) {
+    oVw = take((size_t)ldu * N * sizeof(float));
+    oZw = take((size_t)ldu * mcols * sizeof(float));
+    oRho = take((size_t)ldu * mcols * sizeof(double));
+    oNorm = take(sizeof(double) * (2 + (size_t)norm_partial_elems()));
+  }
   ws_bytes = off;
   hipError_t e = hipMalloc(&ws, ws_bytes);
   if (e != hipSuccess) {
@@ -54,12 +104,23 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   }
   U = ws + oU;
   gamma = reinterpret_cast<double*>(ws + oGamma);
-  part[0] = reinterpret_cast<double*>(ws + oP0);
-  part[1] = reinterpret_cast<double*>(ws + oP1);
   status = reinterpret_cast<unsigned*>(ws + oStat);
   G = reinterpret_cast<double*>(ws + oG);
-  gram_partial = reinterpret_cast<double*>(ws + oGP);
-  // The status word starts at zero.
+  tn_part = reinterpret_cast<double*>(ws + oTn);
+  if (!blocked) {
+    part[0] = reinterpret_cast<double*>(ws + oP0);
+    part[1] = reinterpret_cast<double*>(ws + oP1);
+  } else {
+    Minv = reinterpret_cast<double*>(ws + oMinv);
+    Pbuf = reinterpret_cast<double*>(ws + oPbuf);
+    Qbuf = reinterpret_cast<double*>(ws + oQbuf);
+  }
+  if (mixed) {
+    Vw = ws + oVw;
+    Zw = ws + oZw;
+    rho = reinterpret_cast<double*>(ws + oRho);
+    norms = reinterpret_cast<double*>(ws + oNorm);
+  }
   ENKF_HIP_CHECK(hipMemsetAsync(ws + oStat, 0, sizeof(unsigned) * 4, stream));
   last.rel_residual = -1.0;
   return ENKF_SUCCESS;
@@ -70,21 +131,9 @@ Plan::~Plan() {
   if (ws) (void)hipFree(ws);
 }
 
-enkf_status Plan::factor() { return factor_plain(); }
+enkf_status Plan::factor() { return desc.algo == ENKF_SM_PLAIN ? factor_plain() : factor_blocked(); }
 
-// Byte and flop model of one sweep launch over m columns of n rows:
-// read and write the m columns, read u_k and v_{k+1} (Step 1: the source
-// columns and r instead of u_k); flops 4 m n (update + look-ahead product).
-static void sweep_model(int64_t n, int m, size_t es, bool step1, bool look, double* by, double* fl) {
-  double cols = 2.0 * m + (look ? 1.0 : 0.0) + (step1 ? 0.0 : 1.0);
-  *by = cols * (double)n * (double)es + (step1 ? 8.0 * (double)n : 0.0);
-  *fl = (double)n * m * (look ? 4.0 : 2.0);
-}
-
-static bool vec_ok(const void* p, int64_t ld, int vw, size_t es) {
-  return p == nullptr || (((uintptr_t)p % (vw * es)) == 0 && (ld % vw) == 0);
-}
-
+// ------------------------------------------------------------------ plain
 enkf_status Plan::factor_plain() {
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
@@ -142,8 +191,8 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
   const int N = desc.n_ens;
   if (nrhs == 0) return ENKF_SUCCESS;
   const int w = level_vw(desc.dtype);
-  const int vw = (vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es) && vec_ok(D, ldd, w, es) && vec_ok(Z, ldz, w, es))
-                     ? w : 1;
+  const int vw =
+      (vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es) && vec_ok(D, ldd, w, es) && vec_ok(Z, ldz, w, es)) ? w : 1;
   LevelArgs a{};
   a.n = n;
   a.vw = vw;
@@ -187,13 +236,181 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
   return ENKF_SUCCESS;
 }
 
-namespace {
-__global__ void clear_words_kernel(unsigned* p, int count) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = 0u;
+// ------------------------------------------------------------------ blocked
+// Panel p covers levels k0 .. k0+bl-1. With U holding R^{-1} V updated by the
+// panels before p:  P = V_K^T [U_K, U_rest];  M = I + P[:, :bl] = L D L^T;
+// U_rest -= U_K (M^{-1} P[:, bl:]).
+enkf_status Plan::factor_blocked() {
+  const int64_t n = desc.n_obs;
+  const int N = desc.n_ens;
+  const size_t wes = dtype_size(wdt);
+  enkf_status st;
+  if (mixed) {
+    st = launch_convert(n, N, static_cast<const double*>(V), ldv, static_cast<float*>(Vw), ldu, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  const void* Vk = vwork();
+  const int64_t ldvk = ldvw();
+  {
+    TimedLaunch tl(&timing, stream, KC_STEP1, 2.0 * n * N * wes + 8.0 * n, (double)n * N);
+    st = launch_scale_rows(wdt, n, N, Vk, ldvk, r, U, ldu, status, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  for (int p = 0; p < npanel; ++p) {
+    const int k0 = p * block;
+    const int bl = std::min(block, N - k0);
+    const int mrest = N - k0 - bl;
+    const void* VK = static_cast<const char*>(Vk) + (size_t)k0 * ldvk * wes;
+    const void* UK = static_cast<const char*>(U) + (size_t)k0 * ldu * wes;
+    void* Ur = static_cast<char*>(U) + (size_t)(k0 + bl) * ldu * wes;
+    {
+      TimedLaunch tl(&timing, stream, KC_GRAM, (double)(2 * bl + mrest) * n * wes, 2.0 * n * bl * (bl + mrest));
+      st = launch_tn(wdt, n, bl, bl + mrest, VK, ldvk, UK, ldu, Pbuf, bl, tn_part, stream);
+      if (st != ENKF_SUCCESS) return st;
+    }
+    {
+      TimedLaunch tl(&timing, stream, KC_PANEL_FACTOR, 0.0, (double)bl * bl * bl + 2.0 * bl * bl * mrest);
+      st = launch_panel_factor(bl, Pbuf, bl, gamma + k0, Minv + (size_t)p * block * block, status, stream);
+      if (st != ENKF_SUCCESS) return st;
+      st = launch_small_gemm(bl, mrest, Minv + (size_t)p * block * block, Pbuf + (size_t)bl * bl, bl, Qbuf, stream);
+      if (st != ENKF_SUCCESS) return st;
+    }
+    if (mrest > 0) {
+      NnArgs a{};
+      a.n = n;
+      a.K = bl;
+      a.m = mrest;
+      a.A = UK;
+      a.lda = ldu;
+      a.Bm = Qbuf;
+      a.ldb = bl;
+      a.scale = 1.0;
+      a.Cin = Ur;
+      a.ldc = ldu;
+      a.Cout = Ur;
+      a.ldo = ldu;
+      TimedLaunch tl(&timing, stream, KC_PANEL_UPDATE, (double)(bl + 2 * mrest) * n * wes, 2.0 * n * bl * mrest);
+      st = launch_nn(wdt, NN_UPDATE, a, stream);
+      if (st != ENKF_SUCCESS) return st;
+    }
+  }
+  return ENKF_SUCCESS;
 }
-}  // namespace
 
+// Z = W^{-1} D in the working type (D may be Z itself).
+enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz) {
+  const int64_t n = desc.n_obs;
+  const size_t wes = dtype_size(wdt);
+  enkf_status st;
+  if (nrhs == 0) return ENKF_SUCCESS;
+  {
+    TimedLaunch tl(&timing, stream, KC_STEP1, 2.0 * n * nrhs * wes + 8.0 * n, (double)n * nrhs);
+    st = launch_scale_rows(wdt, n, nrhs, D, ldd, r, Z, ldz, status, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  const void* Vk = vwork();
+  const int64_t ldvk = ldvw();
+  for (int p = 0; p < npanel; ++p) {
+    const int k0 = p * block;
+    const int bl = std::min(block, desc.n_ens - k0);
+    const void* VK = static_cast<const char*>(Vk) + (size_t)k0 * ldvk * wes;
+    const void* UK = static_cast<const char*>(U) + (size_t)k0 * ldu * wes;
+    {
+      TimedLaunch tl(&timing, stream, KC_GRAM, (double)(bl + nrhs) * n * wes, 2.0 * n * bl * nrhs);
+      st = launch_tn(wdt, n, bl, nrhs, VK, ldvk, Z, ldz, Pbuf, bl, tn_part, stream);
+      if (st != ENKF_SUCCESS) return st;
+    }
+    {
+      TimedLaunch tl(&timing, stream, KC_PANEL_FACTOR, 0.0, 2.0 * bl * bl * nrhs);
+      st = launch_small_gemm(bl, nrhs, Minv + (size_t)p * block * block, Pbuf, bl, Qbuf, stream);
+      if (st != ENKF_SUCCESS) return st;
+    }
+    NnArgs a{};
+    a.n = n;
+    a.K = bl;
+    a.m = nrhs;
+    a.A = UK;
+    a.lda = ldu;
+    a.Bm = Qbuf;
+    a.ldb = bl;
+    a.scale = 1.0;
+    a.Cin = Z;
+    a.ldc = ldz;
+    a.Cout = Z;
+    a.ldo = ldz;
+    TimedLaunch tl(&timing, stream, KC_PANEL_UPDATE, (double)(bl + 2 * nrhs) * n * wes, 2.0 * n * bl * nrhs);
+    st = launch_nn(wdt, NN_UPDATE, a, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  return ENKF_SUCCESS;
+}
+
+// Mixed precision: Z0 = W~^{-1} D with FP32 panels, then Z += W~^{-1} rho
+// with rho = D - (R Z + V (V^T Z)) formed in FP64.
+enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync) {
+  const int64_t n = desc.n_obs;
+  const int N = desc.n_ens;
+  last.refine_iters = 0;
+  last.rel_residual = -1.0;
+  if (nrhs == 0) return ENKF_SUCCESS;
+  float* W = static_cast<float*>(Zw);
+  enkf_status st = launch_convert(n, nrhs, static_cast<const double*>(D), ldd, W, ldu, stream);
+  if (st != ENKF_SUCCESS) return st;
+  st = solve_blocked(nrhs, W, ldu, W, ldu);
+  if (st != ENKF_SUCCESS) return st;
+  st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, false, stream);
+  if (st != ENKF_SUCCESS) return st;
+  const int maxit = desc.refine_max_iter;
+  for (int it = 0; it <= maxit; ++it) {
+    if (!sync && it == maxit) break;
+    // rho = D - (r o Z + V (V^T Z)), FP64
+    {
+      TimedLaunch tl(&timing, stream, KC_RESIDUAL, (double)(N + nrhs) * n * 8.0, 2.0 * n * N * nrhs);
+      st = launch_tn(ENKF_F64, n, N, nrhs, V, ldv, Z, ldz, G, N, tn_part, stream);
+      if (st != ENKF_SUCCESS) return st;
+    }
+    {
+      NnArgs a{};
+      a.n = n;
+      a.K = N;
+      a.m = nrhs;
+      a.A = V;
+      a.lda = ldv;
+      a.Bm = G;
+      a.ldb = N;
+      a.scale = 1.0;
+      a.Cin = Z;
+      a.ldc = ldz;
+      a.Cout = rho;
+      a.ldo = ldu;
+      a.Din = D;
+      a.ldd = ldd;
+      a.r = r;
+      TimedLaunch tl(&timing, stream, KC_RESIDUAL, (double)(N + 3 * nrhs) * n * 8.0, 2.0 * n * N * nrhs);
+      st = launch_nn(ENKF_F64, NN_RESIDUAL, a, stream);
+      if (st != ENKF_SUCCESS) return st;
+    }
+    if (sync) {
+      st = launch_sumsq2(n, nrhs, rho, ldu, static_cast<const double*>(D), ldd, norms + 2, norms, stream);
+      if (st != ENKF_SUCCESS) return st;
+      double h[2];
+      ENKF_HIP_CHECK(hipMemcpyAsync(h, norms, sizeof(h), hipMemcpyDeviceToHost, stream));
+      ENKF_HIP_CHECK(hipStreamSynchronize(stream));
+      last.rel_residual = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+      if (last.rel_residual <= desc.refine_tol || it == maxit) break;
+    }
+    st = launch_convert(n, nrhs, rho, ldu, W, ldu, stream);
+    if (st != ENKF_SUCCESS) return st;
+    st = solve_blocked(nrhs, W, ldu, W, ldu);
+    if (st != ENKF_SUCCESS) return st;
+    st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, true, stream);
+    if (st != ENKF_SUCCESS) return st;
+    last.refine_iters = it + 1;
+  }
+  return ENKF_SUCCESS;
+}
+
+// ------------------------------------------------------------------ common
 // A fill kernel rather than a memset, so the sequence stays valid under
 // stream capture.
 enkf_status Plan::clear_status() {
@@ -209,11 +426,26 @@ enkf_status Plan::read_status(unsigned* st) {
 }
 
 enkf_status Plan::solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, enkf_sm_info* info) {
-  enkf_status st = solve_plain(nrhs, D, ldd, Z, ldz);
+  enkf_status st;
+  if (desc.algo == ENKF_SM_PLAIN) {
+    st = solve_plain(nrhs, D, ldd, Z, ldz);
+    last.refine_iters = 0;
+    last.rel_residual = -1.0;
+  } else if (mixed) {
+    st = solve_mixed(nrhs, D, ldd, Z, ldz, info != nullptr);
+  } else {
+    st = solve_blocked(nrhs, D, ldd, Z, ldz);
+    last.refine_iters = 0;
+    last.rel_residual = -1.0;
+  }
   if (st != ENKF_SUCCESS) return st;
-  last.refine_iters = 0;
-  last.rel_residual = -1.0;
-  if (info) return get_info(info);
+  if (info) {
+    st = get_info(info);
+    if (st != ENKF_SUCCESS) return st;
+    if (mixed && desc.refine_tol > 0.0 && nrhs > 0 && !(last.rel_residual <= desc.refine_tol))
+      return fail(ENKF_ERR_NO_CONVERGENCE,
+                  "refinement stopped at relative residual " + std::to_string(last.rel_residual));
+  }
   return ENKF_SUCCESS;
 }
 
@@ -222,16 +454,25 @@ enkf_status Plan::analysis(int64_t n_state, const void* XB, int64_t ldx, const v
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
   {
-    const double by = 2.0 * (double)n * N * es;
-    const double fl = 2.0 * (double)n * N * N;
-    TimedLaunch tl(&timing, stream, KC_GRAM, by, fl);
-    enkf_status st = launch_gram(desc.dtype, n, N, N, V, ldv, Z, ldz, G, N, gram_partial, stream);
+    TimedLaunch tl(&timing, stream, KC_GRAM, 2.0 * (double)n * N * es, 2.0 * (double)n * N * N);
+    enkf_status st = launch_tn(desc.dtype, n, N, N, V, ldv, Z, ldz, G, N, tn_part, stream);
     if (st != ENKF_SUCCESS) return st;
   }
-  const double by = 2.0 * (double)n_state * N * es;
-  const double fl = 2.0 * (double)n_state * N * N;
-  TimedLaunch tl(&timing, stream, KC_ANALYSIS, by, fl);
-  return launch_analysis(desc.dtype, n_state, N, XB, ldx, G, 1.0 / std::sqrt((double)(N - 1)), XA, ldxa, stream);
+  NnArgs a{};
+  a.n = n_state;
+  a.K = N;
+  a.m = N;
+  a.A = XB;
+  a.lda = ldx;
+  a.Bm = G;
+  a.ldb = N;
+  a.scale = 1.0 / std::sqrt((double)(N - 1));
+  a.Cin = XB;
+  a.ldc = ldx;
+  a.Cout = XA;
+  a.ldo = ldxa;
+  TimedLaunch tl(&timing, stream, KC_ANALYSIS, 2.0 * (double)n_state * N * es, 2.0 * (double)n_state * N * N);
+  return launch_nn(desc.dtype, NN_ANALYSIS, a, stream);
 }
 
 enkf_status Plan::get_info(enkf_sm_info* info) {
@@ -245,7 +486,8 @@ enkf_status Plan::get_info(enkf_sm_info* info) {
   out.gamma_max = *std::max_element(g.begin(), g.end());
   out.device_status = (int32_t)st;
   *info = out;
-  if (st != 0) return fail(static_cast<enkf_status>(st), "a kernel latched an error (r_i or gamma_k not finite or not > 0)");
+  if (st != 0)
+    return fail(static_cast<enkf_status>(st), "a kernel latched an error (r_i or gamma_k not finite or not > 0)");
   return ENKF_SUCCESS;
 }
 

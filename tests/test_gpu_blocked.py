@@ -1,0 +1,88 @@
+"""Parity of the blocked and mixed-precision HIP paths with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, fp64_gate, host, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _pk():
+    import paper_1302_3876_amd as pk
+    return pk
+
+
+@pytest.mark.parametrize("n,N,b,nrhs", [(64, 1, 1, 1), (1000, 17, 5, 17), (4099, 33, 8, 7), (16384, 96, 32, 96),
+                                        (16384, 96, 96, 96), (70001, 40, 40, 40), (3, 50, 16, 50),
+                                        (9000, 130, 64, 130)])
+def test_blocked_fp64_matches_oracle(n, N, b, nrhs):
+    import torch
+    print(f"blocked fp64 n={n} N={N} b={b} nrhs={nrhs}", flush=True)
+    r, V, D = synth.small_vd(n, N, seed=3000 + n + N + b, nrhs=nrhs)
+    plan = _pk().Plan(dev(r), dev(V), algo="blocked", block=b, max_nrhs=nrhs)
+    Z, info = plan.solve(dev(D), info=True)
+    torch.cuda.synchronize()
+    ref = oracle.sm_solve(r, V, D)
+    fp64_gate(r, V, D, host(Z), ref["Z"])
+    g, _ = plan.pivots()
+    # the LDL^T pivots of each panel are the gammas of its levels
+    assert np.allclose(g, ref["gamma"], rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("n,N,b", [(4099, 33, 16), (65536, 64, 64)])
+def test_blocked_fp32_matches_oracle(n, N, b):
+    import torch
+    r, V, D = synth.small_vd(n, N, seed=4000 + n, r_range=(0.005, 0.02), v_scale=0.3)
+    plan = _pk().Plan(dev(r), dev(V, torch.float32), algo="blocked", block=b)
+    Z = plan.solve(dev(D, torch.float32))
+    torch.cuda.synchronize()
+    ref = oracle.sm_solve(r, V.astype(np.float32).astype(np.float64), D.astype(np.float32).astype(np.float64))
+    assert rel(host(Z), ref["Z"]) < 1e-4
+
+
+@pytest.mark.parametrize("n,N,b", [(20000, 32, 16), (131072, 64, 32)])
+def test_mixed_f32_refines_to_fp64_accuracy(n, N, b):
+    import torch
+    print(f"mixed f32 n={n} N={N} b={b}", flush=True)
+    w = synth.direct_vd_workload("c3-small", n, N, seed=5000 + n)
+    plan = _pk().Plan(dev(w.r), dev(w.V), algo="blocked", math="f32", block=b, refine_max_iter=6,
+                      refine_tol=1e-11)
+    Z, info = plan.solve(dev(w.D), info=True)
+    torch.cuda.synchronize()
+    print(info, flush=True)
+    assert info["refine_iters"] >= 1 and info["rel_residual"] <= 1e-11
+    ref = oracle.sm_solve(w.r, w.V, w.D)
+    fp64_gate(w.r, w.V, w.D, host(Z), ref["Z"])
+
+
+def test_blocked_analysis_matches_plain():
+    import torch
+    pk = _pk()
+    w = synth.c2(n_state=65536, n_ens=48)
+    XB = dev(w.XB)
+    V, D = pk.enkf_build_vd(XB, dev(w.obs_idx), dev(w.y), dev(w.E))
+    plan = pk.Plan(dev(w.r), V, algo="blocked", block=16)
+    Z = plan.solve(D)
+    XA = plan.analysis(XB, Z)
+    torch.cuda.synchronize()
+    Vo, Do = oracle.build_vd(w.XB, w.obs_idx, w.y, w.E)
+    Zo = oracle.sm_solve(w.r, Vo, Do)["Z"]
+    fp64_gate(w.r, Vo, Do, host(Z), Zo)
+    XAo = oracle.analysis(w.XB, Vo, Zo)
+    assert rel(host(XA) - w.XB, XAo - w.XB) < 1e-9
+
+
+def test_refactor_reuses_plan():
+    import torch
+    pk = _pk()
+    r1, V1, D1 = synth.small_vd(5000, 20, seed=1)
+    r2, V2, D2 = synth.small_vd(5000, 20, seed=2)
+    for algo in ("plain", "blocked"):
+        plan = pk.Plan(dev(r1), dev(V1), algo=algo, block=8 if algo == "blocked" else 0)
+        r2d, V2d = dev(r2), dev(V2)
+        plan.refactor(r2d, V2d)
+        Z = plan.solve(dev(D2))
+        torch.cuda.synchronize()
+        fp64_gate(r2, V2, D2, host(Z), oracle.sm_solve(r2, V2, D2)["Z"])
