@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
-"""Benchmark of one EnKF analysis step on one MI355X.
+"""Benchmark of the EnKF analysis on one MI355X.
 
-A step is the whole hot path on one batch of synthetic input already resident
-in HBM: V and D from the background ensemble, the factorisation of
-(R + V V^T) by the iterative Sherman-Morrison formula, the solve for Z and the
-analysis update X^A. Default workload: the Lorenz-96 ring with n_state =
+Default workload (the headline line): the Lorenz-96 ring with n_state =
 1,048,576, N = 96 members, every 4th variable observed (n_obs = 262,144),
-R = diag(U(0.005, 0.02)), plain FP64.
+R = diag(U(0.005, 0.02)). A step is the whole hot path on inputs already
+resident in HBM: V and D from the background ensemble, the factorisation of
+(R + V V^T) by the iterative Sherman-Morrison formula, the solve for Z and the
+analysis update X^A. `value` is plain FP64 steps per second; the same run
+also times the other forms (plain FP32, blocked FP64, FP32-panel mixed
+precision with FP64 refinement) on the same inputs and reports each one's
+residual.
 
-Prints ONE JSON line (rank 0) with the throughput in analysis solves/s, the
-roofline record of the dominant kernel (the per-level solve sweep, HBM-bound)
-and the FP64 CPU oracle timed on the host as a baseline.
+--workload c3: n_obs = 2,097,152, N = 256, V and D drawn directly; a step is
+factorisation + solve (no ensemble), for the plain, blocked and mixed forms.
+
+Prints ONE JSON line with the roofline record of the dominant kernel of the
+headline form and the FP64 CPU oracle timed on the host as a baseline.
 """
 from __future__ import annotations
 
@@ -24,7 +29,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}
 METRIC = "analysis solves/sec + HBM GB/s or MFMA TFLOP/s, mixed vs plain FP64 at stated residual"
+CLASSES = ("factor_sweep", "solve_sweep", "build", "analysis", "gram", "panel_update", "panel_factor", "residual",
+           "step1")
 
 
 def parse():
@@ -32,12 +40,160 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
-    ap.add_argument("--n-state", type=int, default=1_048_576)
-    ap.add_argument("--n-ens", type=int, default=96)
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2")
+    ap.add_argument("--forms", default="", help="comma list; default: every form of the workload")
+    ap.add_argument("--block", type=int, default=0, help="panel width of the blocked forms (0: automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
     return ap.parse_args()
+
+
+FORMS = {
+    # name: (algo, storage, math, refine)
+    "plain_f64": ("plain", "f64", "f64", 0),
+    "plain_f32": ("plain", "f32", "f32", 0),
+    "blocked_f64": ("blocked", "f64", "f64", 0),
+    "blocked_f32": ("blocked", "f32", "f32", 0),
+    "mixed_f32": ("blocked", "f64", "f32", 3),
+}
+DEFAULT_FORMS = {"c2": ["plain_f64", "plain_f32", "blocked_f64", "mixed_f32"],
+                 "c3": ["blocked_f64", "mixed_f32", "plain_f64"]}
+
+
+def gpu_inputs(w, dtype, pk, torch):
+    d = {"r": torch.as_tensor(w.r).cuda()}
+    if w.XB is not None:
+        d["XB"] = pk.to_colmajor(w.XB, dtype=dtype)
+        d["E"] = pk.to_colmajor(w.E, dtype=dtype)
+        d["obs"] = torch.as_tensor(w.obs_idx).cuda()
+        d["y"] = torch.as_tensor(w.y).cuda()
+        d["V"] = pk.colmajor(w.n_obs, w.n_ens, dtype)
+        d["D"] = pk.colmajor(w.n_obs, w.n_ens, dtype)
+        d["XA"] = pk.colmajor(w.n_state, w.n_ens, dtype)
+    else:
+        d["V"] = pk.to_colmajor(w.V, dtype=dtype)
+        d["D"] = pk.to_colmajor(w.D, dtype=dtype)
+    d["Z"] = pk.colmajor(w.n_obs, w.n_ens, dtype)
+    return d
+
+
+def run_form(name, w, args, pk, torch, cache):
+    import numpy as np
+    algo, storage, math, refine = FORMS[name]
+    tdt = torch.float64 if storage == "f64" else torch.float32
+    if storage not in cache:
+        cache.clear()
+        torch.cuda.empty_cache()
+        cache[storage] = gpu_inputs(w, tdt, pk, torch)
+    g = cache[storage]
+    full = "XB" in g
+    if full:
+        pk.enkf_build_vd(g["XB"], g["obs"], g["y"], g["E"], g["V"], g["D"])
+    block = args.block if algo == "blocked" else 0
+    plan = pk.Plan(g["r"], g["V"], algo=algo, math=math, block=block, refine_max_iter=refine, refine_tol=0.0)
+
+    def step():
+        if full:
+            pk.enkf_build_vd(g["XB"], g["obs"], g["y"], g["E"], g["V"], g["D"])
+        plan.refactor(g["r"], g["V"])
+        plan.solve(g["D"], g["Z"])
+        if full:
+            plan.analysis(g["XB"], g["Z"], g["XA"])
+
+    steps = args.steps if not (name == "plain_f64" and args.workload == "c3") else max(2, args.steps // 10)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    info = plan.info()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    print(f"[bench] {name}: {ms:.3f} ms/step over {steps} steps", file=sys.stderr, flush=True)
+    # per-kernel durations, HIP events on the plan's stream, same workload
+    plan.set_timing(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    kern = {}
+    for c in CLASSES:
+        t = plan.timing(c)
+        if t["launches"] == 0:
+            continue
+        kern[c] = {"ms_per_step": round(t["ms"] / steps, 4), "launches_per_step": t["launches"] // steps,
+                   "avg_launch_us": round(1e3 * t["ms"] / t["launches"], 2),
+                   "alg_bytes_per_launch": t["bytes"] / t["launches"],
+                   "alg_flops_per_launch": t["flops"] / t["launches"],
+                   "GB/s": round(t["bytes"] / (t["ms"] * 1e-3) / 1e9, 1) if t["ms"] > 0 else None,
+                   "TFLOP/s": round(t["flops"] / (t["ms"] * 1e-3) / 1e12, 3) if t["ms"] > 0 else None}
+    plan.set_timing(False)
+    # accuracy of the device result: FP64 residual of the system solved,
+    # formed on the host with numpy (a diagnostic, not part of the path)
+    Vh = np.asfortranarray(g["V"].cpu().numpy().astype(np.float64))
+    Dh = np.asfortranarray(g["D"].cpu().numpy().astype(np.float64))
+    Zh = np.asfortranarray(g["Z"].cpu().numpy().astype(np.float64))
+    rho = Dh - w.r[:, None] * Zh - Vh @ (Vh.T @ Zh)
+    relres = float(np.linalg.norm(rho) / np.linalg.norm(Dh))
+    del Vh, Dh, Zh, rho
+    out = {"ms_per_step": round(ms, 4), "solves_per_s": round(1000.0 / ms, 3), "algo": algo, "storage": storage,
+           "math": math, "refine_iters": refine, "block": (args.block or min(w.n_ens, 128)) if algo == "blocked" else 1,
+           "rel_residual": relres, "gamma_range": [info["gamma_min"], info["gamma_max"]], "kernels": kern}
+    plan.close()
+    return out
+
+
+def roofline_of(form, name):
+    k = form["kernels"]
+    if form["algo"] == "plain":
+        c = k["solve_sweep"]
+        ach = c["alg_bytes_per_launch"] / (c["avg_launch_us"] * 1e-6) / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"level_kernel ({name}: solve sweep, one launch per level)",
+                "avg_launch_us": c["avg_launch_us"], "alg_bytes_per_launch": c["alg_bytes_per_launch"]}
+    c = k["gram"]
+    ach = c["alg_flops_per_launch"] / (c["avg_launch_us"] * 1e-6) / 1e12
+    peak = MFMA_PEAK_TFLOPS[form["math"] if form["math"] in MFMA_PEAK_TFLOPS else "f32"]
+    return {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+            "traffic": None, "kernel": f"tn_partial_kernel ({name}: panel products V_K^T X)",
+            "avg_launch_us": c["avg_launch_us"], "alg_flops_per_launch": c["alg_flops_per_launch"]}
+
+
+def cpu_baseline(w, args):
+    """The FP64 oracle on the host. c2: whole analysis steps of the same
+    workload. c3: the solve on the first n/32 observations (the solve costs
+    3(N^2 n + N n) operations, linear in n), scaled to the full n."""
+    import oracle
+    reps, c0 = 0, time.perf_counter()
+    scale = 1.0
+    if w.XB is None:
+        ns = max(1, w.n_obs // 32)
+        scale = w.n_obs / ns
+        r_s, V_s, D_s = w.r[:ns].copy(), w.V[:ns].copy(order="F"), w.D[:ns].copy(order="F")
+        c0 = time.perf_counter()
+    while True:
+        if w.XB is not None:
+            Vo, Do = oracle.build_vd(w.XB, w.obs_idx, w.y, w.E)
+            Zo = oracle.sm_solve(w.r, Vo, Do)["Z"]
+            oracle.analysis(w.XB, Vo, Zo)
+        else:
+            oracle.sm_solve(r_s, V_s, D_s)
+        reps += 1
+        el = time.perf_counter() - c0
+        if el >= args.cpu_budget_s or reps >= 5:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    if w.XB is not None:
+        what = f"{reps} whole analysis step(s) (build V,D + solve + analysis) of the same workload, FP64, {el:.1f} s"
+    else:
+        what = (f"{reps} solve(s) on the first {w.n_obs // 32} of {w.n_obs} observations, FP64, {el:.1f} s, "
+                f"time scaled by {scale:.0f} (cost linear in n)")
+    return {"value": round(reps / (el * scale), 5), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": what}
 
 
 def main():
@@ -46,132 +202,52 @@ def main():
         print("bench.py measures one GPU only: the analysis path is built and timed on a single MI355X; "
               "sharding across GPUs is described in DESIGN.md but not built. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
     import torch
 
     import paper_1302_3876_amd as pk
     import synth
 
     t0 = time.time()
-    w = synth.c2(n_state=args.n_state, n_ens=args.n_ens)
-    print(f"[bench] inputs generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    tdt = torch.float64 if args.dtype == "f64" else torch.float32
-    es = 8 if args.dtype == "f64" else 4
-    XB = pk.to_colmajor(w.XB, dtype=tdt)
-    E = pk.to_colmajor(w.E, dtype=tdt)
-    obs = torch.as_tensor(w.obs_idx).cuda()
-    y = torch.as_tensor(w.y).cuda()
-    r = torch.as_tensor(w.r).cuda()
-    n_state, N, n_obs = w.n_state, w.n_ens, w.n_obs
-    V = pk.colmajor(n_obs, N, tdt)
-    D = pk.colmajor(n_obs, N, tdt)
-    Z = pk.colmajor(n_obs, N, tdt)
-    XA = pk.colmajor(n_state, N, tdt)
-
-    pk.enkf_build_vd(XB, obs, y, E, V, D)
-    plan = pk.Plan(r, V)
-
-    def step():
-        pk.enkf_build_vd(XB, obs, y, E, V, D)
-        plan.refactor(r, V)
-        plan.solve(D, Z)
-        plan.analysis(XB, Z, XA)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    info = plan.info()   # raises if a kernel latched an error
-
-    # timed region: K whole steps, bracketed by device synchronisation
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_total = ev0.elapsed_time(ev1)
-    ms_per_step = ms_total / args.steps
-    print(f"[bench] {args.steps} steps in {ms_total:.2f} ms (host wall {wall * 1e3:.2f} ms)", file=sys.stderr,
-          flush=True)
-
-    # per-kernel durations with HIP events on the plan's stream (the current
-    # stream), over K more steps of the same workload
-    plan.set_timing(True)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    kc = {c: plan.timing(c) for c in ("factor_sweep", "solve_sweep", "analysis", "gram")}
-    plan.set_timing(False)
-    sw = kc["solve_sweep"]
-    avg_ms = sw["ms"] / max(sw["launches"], 1)
-    bytes_per_launch = sw["bytes"] / max(sw["launches"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "level_kernel (solve sweep, one launch per level)",
-                "avg_launch_us": round(avg_ms * 1e3, 2), "alg_bytes_per_launch": bytes_per_launch}
-    breakdown = {}
-    for c, d in kc.items():
-        per = d["ms"] / args.steps
-        breakdown[c] = {"ms_per_step": round(per, 4), "launches_per_step": d["launches"] // args.steps,
-                        "GB/s": round(d["bytes"] / (d["ms"] * 1e-3) / 1e9, 1) if d["ms"] > 0 else None,
-                        "TFLOP/s": round(d["flops"] / (d["ms"] * 1e-3) / 1e12, 3) if d["ms"] > 0 else None}
-
-    # accuracy of this step's solve, from the device result (host FP64 check)
-    cpu_baseline = None
-    relres = None
-    if not args.no_cpu_baseline:
-        import oracle
-        Zh = Z.cpu().numpy().astype(np.float64)
-        Vh = V.cpu().numpy().astype(np.float64)
-        Dh = D.cpu().numpy().astype(np.float64)
-        relres = oracle.rel_residual(w.r, Vh, Zh, Dh)
-        # the oracle on the host: whole steps of the same workload until the
-        # budget is used (at least one)
-        XBh = XB.cpu().numpy().astype(np.float64)
-        Eh = E.cpu().numpy().astype(np.float64)
-        reps, c0 = 0, time.perf_counter()
-        while True:
-            Vo, Do = oracle.build_vd(XBh, w.obs_idx, w.y, Eh)
-            Zo = oracle.sm_solve(w.r, Vo, Do)["Z"]
-            oracle.analysis(XBh, Vo, Zo)
-            reps += 1
-            el = time.perf_counter() - c0
-            if el >= args.cpu_budget_s or reps >= 5:
-                break
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-        cpu_baseline = {"value": round(reps / el, 4), "unit": "solves/s", "cores": threads, "kind": "oracle",
-                        "sample": f"{reps} whole analysis step(s) (build V,D + solve + analysis) of the same "
-                                  f"workload in FP64, {el:.1f} s"}
-
-    value = 1000.0 / ms_per_step
+    w = synth.c2() if args.workload == "c2" else synth.c3()
+    print(f"[bench] {args.workload} inputs generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    names = [f for f in args.forms.split(",") if f] or DEFAULT_FORMS[args.workload]
+    cache = {}
+    forms = {}
+    for name in names:
+        forms[name] = run_form(name, w, args, pk, torch, cache)
+    cache.clear()
+    head = names[0]
+    primary = forms[head]
+    base = None if args.no_cpu_baseline else cpu_baseline(w, args)
+    if args.workload == "c2":
+        wl = (f"Lorenz-96 ring n_state={w.n_state}, N={w.n_ens}, n_obs={w.n_obs} (every 4th variable), "
+              f"R=diag(U(0.005,0.02)); step = build V,D + factor + solve + analysis update; {head}")
+    else:
+        wl = (f"n_obs={w.n_obs}, N={w.n_ens}, V_ij = N(0,1) s_i/sqrt(N-1), s_i~U(0.5,2), R=diag(U(0.01,0.1)), "
+              f"D~N(0,1); step = factor + solve; {head}")
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": primary["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": primary["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.dtype,
-        "data": "synthetic (seeded Lorenz-96 ensemble, perturbed observations)",
-        "config": {"workload": f"Lorenz-96 ring n_state={n_state}, N={N}, n_obs={n_obs} (every 4th variable), "
-                               f"R=diag(U(0.005,0.02)); plain iterative Sherman-Morrison; step = build V,D + "
-                               f"factor + solve + analysis update",
-                   "n_state": n_state, "n_ens": N, "n_obs": n_obs, "algo": "plain", "storage": args.dtype},
-        "roofline": roofline,
-        "cpu_baseline": cpu_baseline,
-        "kernels": breakdown,
-        "rel_residual": relres,
-        "gamma_range": [info["gamma_min"], info["gamma_max"]],
+        "dtype": primary["storage"],
+        "data": "synthetic (seeded; Lorenz-96 ensemble and perturbed observations for c2, direct V/D draws for c3)",
+        "config": {"workload": wl, "name": args.workload, "n_state": w.n_state, "n_ens": w.n_ens, "n_obs": w.n_obs,
+                   "form": head},
+        "roofline": roofline_of(primary, head),
+        "cpu_baseline": base,
+        "rel_residual": primary["rel_residual"],
+        "forms": forms,
     }
+    if "plain_f64" in forms:
+        p = forms["plain_f64"]["ms_per_step"]
+        out["speedup_vs_plain_f64"] = {k: round(p / v["ms_per_step"], 3) for k, v in forms.items()}
     print(json.dumps(out), flush=True)
 
 

@@ -176,9 +176,10 @@ enkf_status enkf_sm_get_pivots(enkf_sm_plan plan, double* gamma_host, int32_t* p
  * those launches (the minimum each launch must move or compute; the byte and
  * flop models are stated next to each kernel). Enabling or disabling clears
  * the totals. enkf_sm_get_timing synchronises on the recorded events.
- * Classes: 0 factor sweeps (plain), 1 solve sweeps (plain), 2 build,
- * 3 analysis update, 4 split-K products, 5 panel updates (blocked),
- * 6 panel factorisations (blocked), 7 FP64 residuals (refinement).
+ * Classes: 0 factor level sweeps (plain), 1 solve level sweeps (plain),
+ * 2 build, 3 analysis update, 4 split-K products, 5 panel updates (blocked),
+ * 6 panel factorisations (blocked), 7 FP64 residuals (refinement),
+ * 8 Step 1 (with the plain form's first look-ahead products).
  */
 enkf_status enkf_sm_set_timing(enkf_sm_plan plan, int32_t enable);
 enkf_status enkf_sm_get_timing(enkf_sm_plan plan, int32_t kernel_class, double* total_ms, int64_t* launches,

@@ -28,7 +28,7 @@ ENKF_FLAG_PIVOT = 0x1
 STATUS = {0: "ENKF_SUCCESS", 1: "ENKF_ERR_INVALID_ARG", 2: "ENKF_ERR_NOT_SPD", 3: "ENKF_ERR_NO_CONVERGENCE",
           4: "ENKF_ERR_HIP", 5: "ENKF_ERR_OUT_OF_MEMORY", 6: "ENKF_ERR_NOT_SUPPORTED"}
 KERNEL_CLASSES = {"factor_sweep": 0, "solve_sweep": 1, "build": 2, "analysis": 3, "gram": 4,
-                  "panel_update": 5, "panel_factor": 6, "residual": 7}
+                  "panel_update": 5, "panel_factor": 6, "residual": 7, "step1": 8}
 
 
 class EnkfError(RuntimeError):

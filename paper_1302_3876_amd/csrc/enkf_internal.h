@@ -19,15 +19,15 @@ constexpr unsigned kStatusNotSpd = ENKF_ERR_NOT_SPD;
 
 // Kernel classes whose launches can be timed with HIP events (measurement).
 enum KernelClass : int {
-  KC_INIT_SWEEP = 0,   // plain: Step 1 + U-updates, one launch per level
-  KC_SOLVE_SWEEP = 1,  // plain: Step 1 + Z-updates, one launch per level
+  KC_INIT_SWEEP = 0,   // plain: U-updates, one launch per level
+  KC_SOLVE_SWEEP = 1,  // plain: Z-updates, one launch per level
   KC_BUILD = 2,        // V, D from the ensemble
   KC_ANALYSIS = 3,     // X^A = X^B + S G (tall GEMM incl. mean)
   KC_GRAM = 4,         // split-K products V^T X (analysis G, residual, panels)
   KC_PANEL_UPDATE = 5, // blocked: X -= U_K Q (+ look-ahead products)
   KC_PANEL_FACTOR = 6, // blocked: b x b LDL^T and solves
   KC_RESIDUAL = 7,     // FP64 residual of the refinement
-  KC_STEP1 = 8,        // blocked: Step 1 row scaling
+  KC_STEP1 = 8,        // Step 1 (R^{-1} V, R^{-1} D) and the plain form's first products
   KC_COUNT = 9
 };
 

@@ -156,7 +156,7 @@ enkf_status Plan::factor_plain() {
   {
     double by, fl;
     sweep_model(n, N, es, true, true, &by, &fl);
-    TimedLaunch tl(&timing, stream, KC_INIT_SWEEP, by, fl);
+    TimedLaunch tl(&timing, stream, KC_STEP1, by, fl);
     enkf_status st = launch_level(desc.dtype, a, stream);
     if (st != ENKF_SUCCESS) return st;
   }
@@ -208,7 +208,7 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
   {
     double by, fl;
     sweep_model(n, nrhs, es, true, true, &by, &fl);
-    TimedLaunch tl(&timing, stream, KC_SOLVE_SWEEP, by, fl);
+    TimedLaunch tl(&timing, stream, KC_STEP1, by, fl);
     enkf_status st = launch_level(desc.dtype, a, stream);
     if (st != ENKF_SUCCESS) return st;
   }
