@@ -54,7 +54,7 @@ FORMS = {
     "plain_f32": ("plain", "f32", "f32", 0),
     "blocked_f64": ("blocked", "f64", "f64", 0),
     "blocked_f32": ("blocked", "f32", "f32", 0),
-    "mixed_f32": ("blocked", "f64", "f32", 3),
+    "mixed_f32": ("blocked", "f64", "f32", 8),
 }
 DEFAULT_FORMS = {"c2": ["plain_f64", "plain_f32", "blocked_f64", "mixed_f32"],
                  "c3": ["blocked_f64", "mixed_f32", "plain_f64"]}
@@ -90,13 +90,20 @@ def run_form(name, w, args, pk, torch, cache):
     if full:
         pk.enkf_build_vd(g["XB"], g["obs"], g["y"], g["E"], g["V"], g["D"])
     block = args.block if algo == "blocked" else 0
-    plan = pk.Plan(g["r"], g["V"], algo=algo, math=math, block=block, refine_max_iter=refine, refine_tol=0.0)
+    # mixed forms refine until the FP64 residual is <= 1e-10 (synchronous
+    # check per refinement step), at most `refine` steps
+    tol = 1e-10 if refine else 0.0
+    plan = pk.Plan(g["r"], g["V"], algo=algo, math=math, block=block, refine_max_iter=refine, refine_tol=tol)
+    last = {}
 
     def step():
         if full:
             pk.enkf_build_vd(g["XB"], g["obs"], g["y"], g["E"], g["V"], g["D"])
         plan.refactor(g["r"], g["V"])
-        plan.solve(g["D"], g["Z"])
+        if refine:
+            _, last["info"] = plan.solve(g["D"], g["Z"], info=True)
+        else:
+            plan.solve(g["D"], g["Z"])
         if full:
             plan.analysis(g["XB"], g["Z"], g["XA"])
 
@@ -140,7 +147,8 @@ def run_form(name, w, args, pk, torch, cache):
     relres = float(np.linalg.norm(rho) / np.linalg.norm(Dh))
     del Vh, Dh, Zh, rho
     out = {"ms_per_step": round(ms, 4), "solves_per_s": round(1000.0 / ms, 3), "algo": algo, "storage": storage,
-           "math": math, "refine_iters": refine, "block": (args.block or min(w.n_ens, 128)) if algo == "blocked" else 1,
+           "math": math, "refine_iters": last["info"]["refine_iters"] if refine else 0,
+           "device_rel_residual": last["info"]["rel_residual"] if refine else None, "block": (args.block or min(w.n_ens, 128)) if algo == "blocked" else 1,
            "rel_residual": relres, "gamma_range": [info["gamma_min"], info["gamma_max"]], "kernels": kern}
     plan.close()
     return out

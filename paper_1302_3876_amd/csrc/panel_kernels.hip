@@ -55,16 +55,19 @@ __global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* 
     for (int i = j + 1 + t; i < b; i += 256) Lm[tri(i, j)] *= inv_d;
     __syncthreads();
   }
-  // T = L^{-1}: row i from rows < i
-  for (int i = 1; i < b; ++i) {
-    for (int j = t; j < i; j += 256) {
+  // T = L^{-1}, column j by forward substitution (one thread per column:
+  // columns are independent, so no barrier inside)
+  for (int j = t; j < b; j += 256) {
+    for (int i = j + 1; i < b; ++i) {
       double s = Lm[tri(i, j)];
       for (int k = j + 1; k < i; ++k) s += Lm[tri(i, k)] * Tm[tri(k, j)];
       Tm[tri(i, j)] = -s;
     }
-    __syncthreads();
   }
-  // M^{-1} = T^T D^{-1} T
+  __syncthreads();
+  // M^{-1} = T^T D^{-1} T (the reciprocal pivots overwrite D)
+  for (int k = t; k < b; k += 256) Lm[tri(k, k)] = 1.0 / Lm[tri(k, k)];
+  __syncthreads();
   for (int e = t; e < b * b; e += 256) {
     const int i = e % b, j = e / b;
     const int k0 = i > j ? i : j;
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* 
     for (int k = k0; k < b; ++k) {
       const double tki = (k == i) ? 1.0 : Tm[tri(k, i)];
       const double tkj = (k == j) ? 1.0 : Tm[tri(k, j)];
-      s += tki * tkj / Lm[tri(k, k)];
+      s += tki * tkj * Lm[tri(k, k)];
     }
     Minv[i + (int64_t)j * b] = s;
   }
