@@ -1,0 +1,79 @@
+/*
+ * enkf_local.h -- batched localized EnKF analyses on one MI355X (gfx950).
+ *
+ * Many independent small analyses, one per state point, each using only the
+ * observations of its own window, run in one kernel launch (captured once
+ * into a HIP graph and replayed). Problem p:
+ *   rows g = (win_start[p] + i) mod n_glob, i = 0 .. win_len[p]-1, of the
+ *   global r, V, D (a cyclic domain);
+ *   Z_p = (R_p + V_p V_p^T)^{-1} D_p        (Section 3, eq. system-to-solve-V)
+ *   xa_p = x^B_s + S_s (V_p^T Z_p),  s = state_idx[p],
+ *   S_s = (x^B_s - mean(x^B_s)) / sqrt(N-1)  (Section 3.1, the SMEnKF update,
+ *   for the single state row s).
+ * Each local solve is the Sherman-Morrison-Woodbury form (eq. SWM) with one
+ * panel of all N levels: M_p = I + V_p^T R_p^{-1} V_p = L D L^T, whose
+ * pivots D are the gamma_k of the iterative formula (Section 3.3), and
+ * V_p^T Z_p = M_p^{-1} V_p^T R_p^{-1} D_p. Products run on FP32 matrix cores
+ * (FP32 storage) with FP64 accumulation across row stages; the pivots and
+ * the N x N solves are FP64.
+ *
+ * Conventions as in enkf_sm.h: column-major, device pointers, stream-ordered,
+ * enkf_status returns; argument errors are found on the host.
+ */
+#ifndef ENKF_LOCAL_H
+#define ENKF_LOCAL_H
+
+#include <stdint.h>
+
+#include "enkf_sm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ENKF_LOCAL_MAX_ENS 64   /* N <= 64 */
+
+typedef struct {
+    int64_t n_glob;   /* observations on the cyclic domain (rows of r, V, D), >= 1 */
+    int32_t n_ens;    /* N, 2 <= N <= ENKF_LOCAL_MAX_ENS */
+    int64_t n_state;  /* rows of X^B */
+    int64_t n_prob;   /* number of local problems, >= 0 */
+    int32_t tune;     /* 1: time the kernel configurations on the first call and keep the fastest; 0: default */
+} enkf_local_desc;
+
+typedef struct enkf_local_plan_s* enkf_local_plan;
+
+/*
+ * Create a plan for a fixed set of windows. win_start, win_len and state_idx
+ * are HOST arrays of n_prob entries (copied): 0 <= win_start < n_glob,
+ * 1 <= win_len <= n_glob, 0 <= state_idx < n_state; violations return
+ * ENKF_ERR_INVALID_ARG. The plan orders the problems longest-first and deals
+ * them to the blocks of the launch (a static schedule). Allocates; the stream
+ * is fixed here.
+ */
+enkf_status enkf_local_init(enkf_local_plan* out, const enkf_local_desc* desc, const int64_t* win_start,
+                            const int64_t* win_len, const int64_t* state_idx, void* stream);
+
+/*
+ * Run every local analysis. r (n_glob, FP64, > 0), V and D (n_glob x N, FP32,
+ * leading dimension ldv), XB (n_state x N, FP32, ldx), XA (n_prob x N, FP32,
+ * ldxa >= n_prob): row p receives xa_p. gamma (FP64, n_prob x N, leading
+ * dimension n_prob) receives the pivots of every problem, or is NULL.
+ * One kernel launch, replayed from a HIP graph; allocates nothing. A pivot
+ * that is not finite or not > 0 latches ENKF_ERR_NOT_SPD, reported by
+ * enkf_local_sync.
+ */
+enkf_status enkf_local_analysis(enkf_local_plan plan, const double* r, const float* V, const float* D, int64_t ldv,
+                                const float* XB, int64_t ldx, float* XA, int64_t ldxa, double* gamma);
+
+/* Synchronise the plan's stream and return any latched device error.
+ * *rows_per_stage and *blocks receive the configuration in use (may be NULL). */
+enkf_status enkf_local_sync(enkf_local_plan plan, int32_t* rows_per_stage, int32_t* blocks);
+
+void enkf_local_destroy(enkf_local_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENKF_LOCAL_H */

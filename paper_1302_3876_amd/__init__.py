@@ -20,6 +20,7 @@ from typing import Optional
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libenkf_sm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "enkf_sm.h")
+HEADER_LOCAL = os.path.join(os.path.dirname(HERE), "include", "enkf_local.h")
 
 ENKF_F64, ENKF_F32 = 0, 1
 ENKF_SM_PLAIN, ENKF_SM_BLOCKED = 0, 1
@@ -42,6 +43,11 @@ class SmDesc(ctypes.Structure):
                 ("algo", ctypes.c_int), ("math", ctypes.c_int), ("block", ctypes.c_int32),
                 ("max_nrhs", ctypes.c_int32), ("refine_max_iter", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class LocalDesc(ctypes.Structure):
+    _fields_ = [("n_glob", ctypes.c_int64), ("n_ens", ctypes.c_int32), ("n_state", ctypes.c_int64),
+                ("n_prob", ctypes.c_int64), ("tune", ctypes.c_int32)]
 
 
 class SmInfo(ctypes.Structure):
@@ -79,12 +85,18 @@ def lib():
                                      ctypes.POINTER(dbl)]
     L.enkf_sm_destroy.argtypes = [vp]
     L.enkf_sm_destroy.restype = None
+    L.enkf_local_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(LocalDesc), vp, vp, vp, vp]
+    L.enkf_local_analysis.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, i64, vp]
+    L.enkf_local_sync.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.enkf_local_destroy.argtypes = [vp]
+    L.enkf_local_destroy.restype = None
     L.enkf_status_string.argtypes = [ctypes.c_int]
     L.enkf_status_string.restype = ctypes.c_char_p
     L.enkf_last_error_message.argtypes = []
     L.enkf_last_error_message.restype = ctypes.c_char_p
     for name in ("enkf_sm_validate_desc", "enkf_build_vd", "enkf_sm_init", "enkf_sm_refactor", "enkf_sm_solve", "enkf_analysis",
-                 "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_set_timing", "enkf_sm_get_timing"):
+                 "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_set_timing", "enkf_sm_get_timing",
+                 "enkf_local_init", "enkf_local_analysis", "enkf_local_sync"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -285,3 +297,55 @@ def enkf_sm_solve(plan: Plan, D, Z=None, info: bool = False):
 
 def enkf_analysis(plan: Plan, XB, Z, XA=None):
     return plan.analysis(XB, Z, XA)
+
+
+class LocalPlan:
+    """Batched localized analyses (enkf_local_init / enkf_local_analysis)."""
+
+    def __init__(self, n_glob: int, n_ens: int, n_state: int, win_start, win_len, state_idx, tune: bool = True):
+        import numpy as np
+        ws = np.ascontiguousarray(win_start, dtype=np.int64)
+        wl = np.ascontiguousarray(win_len, dtype=np.int64)
+        si = np.ascontiguousarray(state_idx, dtype=np.int64)
+        self.n_prob, self.n_ens = ws.shape[0], n_ens
+        self.desc = LocalDesc(n_glob, n_ens, n_state, self.n_prob, 1 if tune else 0)
+        self._handle = ctypes.c_void_p()
+        _check(lib().enkf_local_init(ctypes.byref(self._handle), ctypes.byref(self.desc),
+                                     ctypes.c_void_p(ws.ctypes.data), ctypes.c_void_p(wl.ctypes.data),
+                                     ctypes.c_void_p(si.ctypes.data), _stream()), "enkf_local_init")
+
+    def analysis(self, r, V, D, XB, XA=None, gamma=None):
+        """Every local analysis in one launch; returns XA (n_prob x N)."""
+        torch = _torch()
+        pV, ldv = _mat(V, "V", ENKF_F32)
+        pD, ldd = _mat(D, "D", ENKF_F32)
+        if ldd != ldv:
+            raise ValueError("V and D must share a leading dimension")
+        pXB, ldx = _mat(XB, "XB", ENKF_F32)
+        if XA is None:
+            XA = colmajor(self.n_prob, self.n_ens, torch.float32, V.device)
+        pXA, ldxa = _mat(XA, "XA", ENKF_F32)
+        pg = None
+        if gamma is not None:
+            pg, ldg = _mat(gamma, "gamma", ENKF_F64)
+            if ldg != self.n_prob:
+                raise ValueError("gamma must have leading dimension n_prob")
+        _check(lib().enkf_local_analysis(self._handle, _vec(r, "r", torch.float64), pV, pD, ldv, pXB, ldx, pXA, ldxa,
+                                         pg), "enkf_local_analysis")
+        return XA
+
+    def sync(self):
+        kc, nb = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().enkf_local_sync(self._handle, ctypes.byref(kc), ctypes.byref(nb)), "enkf_local_sync")
+        return {"rows_per_stage": kc.value, "blocks": nb.value}
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            lib().enkf_local_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,84 @@
+"""Batched localized analyses (enkf_local_*) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _pk():
+    import paper_1302_3876_amd as pk
+    return pk
+
+
+def _inputs(w):
+    import torch
+    V, D = oracle.build_vd(w.XB, w.obs_idx, w.y, w.E)
+    V32, D32 = V.astype(np.float32), D.astype(np.float32)
+    XB32 = w.XB.astype(np.float32)
+    return V32, D32, XB32, dev(V32, torch.float32), dev(D32, torch.float32), dev(XB32, torch.float32)
+
+
+def _check(w, xa, V32, D32, XB32, start, ln, pts, tol):
+    ref = oracle.local_analysis(w.r, V32.astype(np.float64), D32.astype(np.float64), XB32.astype(np.float64),
+                                start, ln, pts)
+    inc = xa - XB32.astype(np.float64)[pts]
+    inc_ref = ref - XB32.astype(np.float64)[pts]
+    err = np.abs(inc - inc_ref).max() / np.abs(inc_ref).max()
+    print({"max_increment_err": err}, flush=True)
+    assert err < tol
+
+
+@pytest.mark.parametrize("n_ens,n_prob,lo,hi,tune", [(64, 300, 16, 512, False), (20, 200, 1, 90, True),
+                                                      (64, 64, 500, 512, True), (2, 50, 1, 40, False)])
+def test_local_matches_oracle(n_ens, n_prob, lo, hi, tune):
+    import torch
+    print(f"local N={n_ens} P={n_prob} n_p in [{lo},{hi}] tune={tune}", flush=True)
+    w = synth.c4(n_ens=n_ens, n_prob=n_prob, lo=lo, hi=hi)
+    start, ln, pts = w.extra["win_start"], w.extra["win_len"], w.extra["state_idx"]
+    V32, D32, XB32, Vd, Dd, XBd = _inputs(w)
+    plan = _pk().LocalPlan(w.n_obs, n_ens, w.n_state, start, ln, pts, tune=tune)
+    gamma = _pk().colmajor(n_prob, n_ens, torch.float64)
+    xa = plan.analysis(dev(w.r), Vd, Dd, XBd, gamma=gamma)
+    cfg = plan.sync()
+    print(cfg, flush=True)
+    _check(w, host(xa), V32, D32, XB32, start, ln, pts, 1e-5)
+    # pivots of a few problems against the iterative formula's gammas
+    g = host(gamma)
+    for p in (0, n_prob // 2, n_prob - 1):
+        rows = (start[p] + np.arange(ln[p])) % w.n_obs
+        ref = oracle.sm_solve(w.r[rows], V32.astype(np.float64)[rows], D32.astype(np.float64)[rows])["gamma"]
+        assert np.allclose(g[p], ref, rtol=1e-4, atol=0)
+
+
+def test_local_full_size_and_graph_replay():
+    import torch
+    print("local c4 full size", flush=True)
+    w = synth.c4()
+    start, ln, pts = w.extra["win_start"], w.extra["win_len"], w.extra["state_idx"]
+    V32, D32, XB32, Vd, Dd, XBd = _inputs(w)
+    plan = _pk().LocalPlan(w.n_obs, w.n_ens, w.n_state, start, ln, pts, tune=True)
+    r = dev(w.r)
+    xa1 = host(plan.analysis(r, Vd, Dd, XBd))
+    # replays of the captured launch, with eager host work between them
+    outs = []
+    for _ in range(3):
+        outs.append(host(plan.analysis(r, Vd, Dd, XBd)))
+        torch.cuda.synchronize()
+    plan.sync()
+    for o in outs:
+        assert np.array_equal(o, xa1)
+    _check(w, xa1, V32, D32, XB32, start, ln, pts, 1e-5)
+
+
+def test_local_rejects_bad_windows():
+    pk = _pk()
+    with pytest.raises(pk.EnkfError):
+        pk.LocalPlan(100, 8, 100, [0, 100], [5, 5], [0, 1])
+    with pytest.raises(pk.EnkfError):
+        pk.LocalPlan(100, 8, 100, [0], [0], [0])
+    with pytest.raises(pk.EnkfError):
+        pk.LocalPlan(100, 65, 100, [0], [5], [0])
