@@ -55,9 +55,11 @@ FORMS = {
     "blocked_f64": ("blocked", "f64", "f64", 0),
     "blocked_f32": ("blocked", "f32", "f32", 0),
     "mixed_f32": ("blocked", "f64", "f32", 8),
+    "mixed_bf16x3": ("blocked", "f64", "bf16x3", 12),
+    "mixed_f16x2": ("blocked", "f64", "f16x2", 12),
 }
 DEFAULT_FORMS = {"c2": ["plain_f64", "plain_f32", "blocked_f64", "mixed_f32"],
-                 "c3": ["blocked_f64", "mixed_f32", "plain_f64"]}
+                 "c3": ["blocked_f64", "mixed_f32", "mixed_bf16x3", "mixed_f16x2", "plain_f64"]}
 
 
 def gpu_inputs(w, dtype, pk, torch):

@@ -390,8 +390,13 @@ enkf_status launch_tn(enkf_dtype dt, int64_t n, int a, int m, const void* A, int
     tn_partial_kernel<float><<<grid, NT, 0, s>>>(n, a, m, (const float*)A, lda, (const float*)B, ldb, partial, rpc,
                                                  tiles_m, vec);
   ENKF_HIP_CHECK(hipGetLastError());
+  return launch_partial_sum(a, m, used, partial, G, ldg, s);
+}
+
+enkf_status launch_partial_sum(int a, int m, int64_t chunks, const double* partial, double* G, int64_t ldg,
+                               hipStream_t s) {
   const int64_t am = (int64_t)a * m;
-  partial_sum_kernel<<<(unsigned)((am + 63) / 64), 256, 0, s>>>(a, m, used, partial, G, ldg);
+  partial_sum_kernel<<<(unsigned)((am + 63) / 64), 256, 0, s>>>(a, m, chunks, partial, G, ldg);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }

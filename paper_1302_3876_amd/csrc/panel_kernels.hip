@@ -93,20 +93,33 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(int b, int m, const dou
   Q[i + j * b] = s;
 }
 
-__global__ __launch_bounds__(256) void convert_kernel(int64_t n, int m, const double* __restrict__ X, int64_t ldx,
-                                                      float* __restrict__ Y, int64_t ldy) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  for (int j = blockIdx.y; j < m; j += gridDim.y) Y[i + (int64_t)j * ldy] = (float)X[i + (int64_t)j * ldx];
+// Scale of a residual block: its root mean square (1 when it is zero or
+// when no sum of squares is given).
+__device__ __forceinline__ double rms_scale(const double* sumsq, double count) {
+  if (!sumsq) return 1.0;
+  const double s = sqrt(sumsq[0] / count);
+  return (s > 0.0 && s < 1e300) ? s : 1.0;
 }
 
-// Z = W (accumulate == 0) or Z += W (accumulate == 1), W in FP32.
-__global__ __launch_bounds__(256) void widen_kernel(int64_t n, int m, const float* __restrict__ W, int64_t ldw,
-                                                    double* __restrict__ Z, int64_t ldz, int accumulate) {
+// Y = X / scale in FP32 (scale = rms of X when sumsq is given), so a
+// shrinking residual stays inside the range of the narrow input types.
+__global__ __launch_bounds__(256) void convert_kernel(int64_t n, int m, const double* __restrict__ X, int64_t ldx,
+                                                      float* __restrict__ Y, int64_t ldy, const double* sumsq) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const double inv = 1.0 / rms_scale(sumsq, (double)n * m);
+  for (int j = blockIdx.y; j < m; j += gridDim.y) Y[i + (int64_t)j * ldy] = (float)(X[i + (int64_t)j * ldx] * inv);
+}
+
+// Z = scale W (accumulate == 0) or Z += scale W (accumulate == 1), W in FP32.
+__global__ __launch_bounds__(256) void widen_kernel(int64_t n, int m, const float* __restrict__ W, int64_t ldw,
+                                                    double* __restrict__ Z, int64_t ldz, int accumulate,
+                                                    const double* sumsq) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double sc = rms_scale(sumsq, (double)n * m);
   for (int j = blockIdx.y; j < m; j += gridDim.y) {
-    const double w = (double)W[i + (int64_t)j * ldw];
+    const double w = sc * (double)W[i + (int64_t)j * ldw];
     double* z = Z + i + (int64_t)j * ldz;
     *z = accumulate ? *z + w : w;
   }
@@ -155,19 +168,20 @@ __global__ __launch_bounds__(64) void sumsq_final_kernel(int nblk, const double*
 
 int norm_partial_elems() { return 2 * NORM_BLOCKS; }
 
-enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float* Y, int64_t ldy, hipStream_t s) {
+enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float* Y, int64_t ldy, const double* sumsq,
+                           hipStream_t s) {
   if (m <= 0) return ENKF_SUCCESS;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)(m < 16 ? m : 16));
-  convert_kernel<<<grid, 256, 0, s>>>(n, m, X, ldx, Y, ldy);
+  convert_kernel<<<grid, 256, 0, s>>>(n, m, X, ldx, Y, ldy, sumsq);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
 
 enkf_status launch_widen(int64_t n, int m, const float* W, int64_t ldw, double* Z, int64_t ldz, bool accumulate,
-                         hipStream_t s) {
+                         const double* sumsq, hipStream_t s) {
   if (m <= 0) return ENKF_SUCCESS;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)(m < 16 ? m : 16));
-  widen_kernel<<<grid, 256, 0, s>>>(n, m, W, ldw, Z, ldz, accumulate ? 1 : 0);
+  widen_kernel<<<grid, 256, 0, s>>>(n, m, W, ldw, Z, ldz, accumulate ? 1 : 0, sumsq);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "enkf_internal.h"
+#include "gemm_mfma.h"
 
 namespace enkf {
 
@@ -68,6 +69,9 @@ struct Plan {
   const void* vwork() const { return mixed ? Vw : V; }
   int64_t ldvw() const { return mixed ? ldu : ldv; }
   const void* vcol(int k) const;  // V column used at level k
+  enkf_status panel_tn(int64_t n, int a, int m, const void* A, int64_t lda, const void* B, int64_t ldb, double* Gout,
+                       int64_t ldg);
+  enkf_status panel_nn(const NnArgs& a);
 };
 
 }  // namespace enkf

@@ -2,9 +2,11 @@
 // solve and analysis, for the plain, blocked and mixed-precision forms.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <limits>
 
+#include "gemm_lowp.h"
 #include "gemm_mfma.h"
 #include "panel.h"
 #include "plan.h"
@@ -37,6 +39,21 @@ void sweep_model(int64_t n, int m, size_t es, bool step1, bool look, double* by,
 
 const void* Plan::vcol(int k) const { return static_cast<const char*>(V) + (size_t)k * (size_t)ldv * es; }
 
+// Panel products in the working type; narrow math types round the FP32
+// operands when they are staged.
+enkf_status Plan::panel_tn(int64_t n, int a, int m, const void* A, int64_t lda, const void* B, int64_t ldb, double* Gout,
+                           int64_t ldg) {
+  if (mixed && desc.math != ENKF_MATH_F32)
+    return launch_tn_lowp(desc.math, n, a, m, static_cast<const float*>(A), lda, static_cast<const float*>(B), ldb,
+                          Gout, ldg, tn_part, stream);
+  return launch_tn(wdt, n, a, m, A, lda, B, ldb, Gout, ldg, tn_part, stream);
+}
+
+enkf_status Plan::panel_nn(const NnArgs& a) {
+  if (mixed && desc.math != ENKF_MATH_F32) return launch_nn_lowp(desc.math, NN_UPDATE, a, stream);
+  return launch_nn(wdt, NN_UPDATE, a, stream);
+}
+
 enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_, int64_t ldv_, hipStream_t s) {
   desc = d;
   r = r_;
@@ -57,8 +74,8 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
     block = d.block > 0 ? d.block : std::min(N, kMaxPanel);
     if (block > kMaxPanel) return fail(ENKF_ERR_NOT_SUPPORTED, "init: panel width above 128");
     npanel = (N + block - 1) / block;
-    if (d.math != ENKF_MATH_F64 && d.math != ENKF_MATH_F32)
-      return fail(ENKF_ERR_NOT_SUPPORTED, "init: this math type is not available yet");
+    if (d.dtype == ENKF_F32 && d.math != ENKF_MATH_F32)
+      return fail(ENKF_ERR_NOT_SUPPORTED, "init: FP32 storage takes FP32 panels (narrower panels refine an FP64 solve)");
   }
   ldu = (int64_t)align_up((size_t)n, 64);
 
@@ -246,7 +263,7 @@ enkf_status Plan::factor_blocked() {
   const size_t wes = dtype_size(wdt);
   enkf_status st;
   if (mixed) {
-    st = launch_convert(n, N, static_cast<const double*>(V), ldv, static_cast<float*>(Vw), ldu, stream);
+    st = launch_convert(n, N, static_cast<const double*>(V), ldv, static_cast<float*>(Vw), ldu, nullptr, stream);
     if (st != ENKF_SUCCESS) return st;
   }
   const void* Vk = vwork();
@@ -265,7 +282,7 @@ enkf_status Plan::factor_blocked() {
     void* Ur = static_cast<char*>(U) + (size_t)(k0 + bl) * ldu * wes;
     {
       TimedLaunch tl(&timing, stream, KC_GRAM, (double)(2 * bl + mrest) * n * wes, 2.0 * n * bl * (bl + mrest));
-      st = launch_tn(wdt, n, bl, bl + mrest, VK, ldvk, UK, ldu, Pbuf, bl, tn_part, stream);
+      st = panel_tn(n, bl, bl + mrest, VK, ldvk, UK, ldu, Pbuf, bl);
       if (st != ENKF_SUCCESS) return st;
     }
     {
@@ -290,7 +307,7 @@ enkf_status Plan::factor_blocked() {
       a.Cout = Ur;
       a.ldo = ldu;
       TimedLaunch tl(&timing, stream, KC_PANEL_UPDATE, (double)(bl + 2 * mrest) * n * wes, 2.0 * n * bl * mrest);
-      st = launch_nn(wdt, NN_UPDATE, a, stream);
+      st = panel_nn(a);
       if (st != ENKF_SUCCESS) return st;
     }
   }
@@ -317,7 +334,7 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
     const void* UK = static_cast<const char*>(U) + (size_t)k0 * ldu * wes;
     {
       TimedLaunch tl(&timing, stream, KC_GRAM, (double)(bl + nrhs) * n * wes, 2.0 * n * bl * nrhs);
-      st = launch_tn(wdt, n, bl, nrhs, VK, ldvk, Z, ldz, Pbuf, bl, tn_part, stream);
+      st = panel_tn(n, bl, nrhs, VK, ldvk, Z, ldz, Pbuf, bl);
       if (st != ENKF_SUCCESS) return st;
     }
     {
@@ -339,7 +356,7 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
     a.Cout = Z;
     a.ldo = ldz;
     TimedLaunch tl(&timing, stream, KC_PANEL_UPDATE, (double)(bl + 2 * nrhs) * n * wes, 2.0 * n * bl * nrhs);
-    st = launch_nn(wdt, NN_UPDATE, a, stream);
+    st = panel_nn(a);
     if (st != ENKF_SUCCESS) return st;
   }
   return ENKF_SUCCESS;
@@ -354,11 +371,11 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
   last.rel_residual = -1.0;
   if (nrhs == 0) return ENKF_SUCCESS;
   float* W = static_cast<float*>(Zw);
-  enkf_status st = launch_convert(n, nrhs, static_cast<const double*>(D), ldd, W, ldu, stream);
+  enkf_status st = launch_convert(n, nrhs, static_cast<const double*>(D), ldd, W, ldu, nullptr, stream);
   if (st != ENKF_SUCCESS) return st;
   st = solve_blocked(nrhs, W, ldu, W, ldu);
   if (st != ENKF_SUCCESS) return st;
-  st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, false, stream);
+  st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, false, nullptr, stream);
   if (st != ENKF_SUCCESS) return st;
   const int maxit = desc.refine_max_iter;
   for (int it = 0; it <= maxit; ++it) {
@@ -390,20 +407,21 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
       st = launch_nn(ENKF_F64, NN_RESIDUAL, a, stream);
       if (st != ENKF_SUCCESS) return st;
     }
+    // ||rho||^2 and ||D||^2: the convergence test and the scale of rho
+    st = launch_sumsq2(n, nrhs, rho, ldu, static_cast<const double*>(D), ldd, norms + 2, norms, stream);
+    if (st != ENKF_SUCCESS) return st;
     if (sync) {
-      st = launch_sumsq2(n, nrhs, rho, ldu, static_cast<const double*>(D), ldd, norms + 2, norms, stream);
-      if (st != ENKF_SUCCESS) return st;
       double h[2];
       ENKF_HIP_CHECK(hipMemcpyAsync(h, norms, sizeof(h), hipMemcpyDeviceToHost, stream));
       ENKF_HIP_CHECK(hipStreamSynchronize(stream));
       last.rel_residual = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
       if (last.rel_residual <= desc.refine_tol || it == maxit) break;
     }
-    st = launch_convert(n, nrhs, rho, ldu, W, ldu, stream);
+    st = launch_convert(n, nrhs, rho, ldu, W, ldu, norms, stream);
     if (st != ENKF_SUCCESS) return st;
     st = solve_blocked(nrhs, W, ldu, W, ldu);
     if (st != ENKF_SUCCESS) return st;
-    st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, true, stream);
+    st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, true, norms, stream);
     if (st != ENKF_SUCCESS) return st;
     last.refine_iters = it + 1;
   }
@@ -443,8 +461,12 @@ enkf_status Plan::solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t l
     st = get_info(info);
     if (st != ENKF_SUCCESS) return st;
     if (mixed && desc.refine_tol > 0.0 && nrhs > 0 && !(last.rel_residual <= desc.refine_tol))
-      return fail(ENKF_ERR_NO_CONVERGENCE,
-                  "refinement stopped at relative residual " + std::to_string(last.rel_residual));
+    {
+      char buf[96];
+      snprintf(buf, sizeof(buf), "refinement stopped at relative residual %.3e after %d steps", last.rel_residual,
+               last.refine_iters);
+      return fail(ENKF_ERR_NO_CONVERGENCE, buf);
+    }
   }
   return ENKF_SUCCESS;
 }

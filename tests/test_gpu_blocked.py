@@ -86,3 +86,33 @@ def test_refactor_reuses_plan():
         Z = plan.solve(dev(D2))
         torch.cuda.synchronize()
         fp64_gate(r2, V2, D2, host(Z), oracle.sm_solve(r2, V2, D2)["Z"])
+
+
+@pytest.mark.parametrize("math", ["f32", "bf16", "f16", "bf16x3", "f16x2"])
+def test_mixed_every_math_well_conditioned(math):
+    # pivots gamma ~ 15: the one-pass 16-bit forms converge only where the
+    # pivots times the input rounding (bf16 4e-3, f16 5e-4) stay well below 1
+    import torch
+    n, N = 1000, 16
+    r, V, D = synth.small_vd(n, N, seed=77, r_range=(0.5, 2.0), v_scale=0.5)
+    plan = _pk().Plan(dev(r), dev(V), algo="blocked", math=math, block=16, refine_max_iter=12, refine_tol=1e-12)
+    Z, info = plan.solve(dev(D), info=True)
+    torch.cuda.synchronize()
+    print(math, info, flush=True)
+    assert info["rel_residual"] <= 1e-12
+    fp64_gate(r, V, D, host(Z), oracle.sm_solve(r, V, D)["Z"])
+
+
+# f16x2 (~22 significant bits) contracts like FP32; bf16x3 (~16 bits) about
+# 0.3 per step on this data, so it needs more steps
+@pytest.mark.parametrize("math,maxit", [("bf16x3", 30), ("f16x2", 8), ("f32", 8)])
+def test_mixed_split_forms_reach_gate_on_c3_like_data(math, maxit):
+    import torch
+    n, N, b = 131072, 64, 32
+    w = synth.direct_vd_workload("c3-small", n, N, seed=6000)
+    plan = _pk().Plan(dev(w.r), dev(w.V), algo="blocked", math=math, block=b, refine_max_iter=maxit,
+                      refine_tol=1e-10)
+    Z, info = plan.solve(dev(w.D), info=True)
+    torch.cuda.synchronize()
+    print(math, info, flush=True)
+    assert info["rel_residual"] <= 1e-10
