@@ -160,6 +160,17 @@ enkf_status enkf_sm_solve(enkf_sm_plan plan, int32_t nrhs, const void* D, int64_
 enkf_status enkf_analysis(enkf_sm_plan plan, int64_t n_state, const void* XB, int64_t ldx, const void* Z,
                           int64_t ldz, void* XA, int64_t ldxa);
 
+/*
+ * The same analysis update with the ensemble in its own storage type and the
+ * n_state x N x N product on a chosen matrix-core input type: x_dtype is the
+ * type of XB and XA; math is ENKF_MATH_F64 (x_dtype F64) or ENKF_MATH_F32,
+ * ENKF_MATH_BF16, ENKF_MATH_F16, ENKF_MATH_BF16X3, ENKF_MATH_F16X2 (x_dtype
+ * F32; accumulation in FP32). G = V^T Z is formed in the plan's storage type
+ * with FP64 accumulation. Z is in the plan's dtype. XA must not overlap XB.
+ */
+enkf_status enkf_analysis_ex(enkf_sm_plan plan, int64_t n_state, enkf_dtype x_dtype, enkf_math math, const void* XB,
+                             int64_t ldx, const void* Z, int64_t ldz, void* XA, int64_t ldxa);
+
 /* Synchronise the plan's stream and report the factor's pivots, the last
  * solve's refinement record and any latched device error. */
 enkf_status enkf_sm_get_info(enkf_sm_plan plan, enkf_sm_info* info);

@@ -78,6 +78,7 @@ def lib():
     L.enkf_sm_solve.argtypes = [vp, i32, vp, i64, vp, i64, ctypes.POINTER(SmInfo)]
     L.enkf_sm_refactor.argtypes = [vp, vp, vp, i64]
     L.enkf_analysis.argtypes = [vp, i64, vp, i64, vp, i64, vp, i64]
+    L.enkf_analysis_ex.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, vp, i64]
     L.enkf_sm_get_info.argtypes = [vp, ctypes.POINTER(SmInfo)]
     L.enkf_sm_get_pivots.argtypes = [vp, vp, vp]
     L.enkf_sm_set_timing.argtypes = [vp, i32]
@@ -95,7 +96,7 @@ def lib():
     L.enkf_last_error_message.argtypes = []
     L.enkf_last_error_message.restype = ctypes.c_char_p
     for name in ("enkf_sm_validate_desc", "enkf_build_vd", "enkf_sm_init", "enkf_sm_refactor", "enkf_sm_solve", "enkf_analysis",
-                 "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_set_timing", "enkf_sm_get_timing",
+                 "enkf_analysis_ex", "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_set_timing", "enkf_sm_get_timing",
                  "enkf_local_init", "enkf_local_analysis", "enkf_local_sync"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -251,6 +252,19 @@ class Plan:
             XA = colmajor(XB.shape[0], XB.shape[1], XB.dtype, XB.device)
         pXA, ldxa = _mat(XA, "XA", self.dtype)
         _check(lib().enkf_analysis(self._handle, XB.shape[0], pXB, ldx, pZ, ldz, pXA, ldxa), "enkf_analysis")
+        return XA
+
+    def analysis_ex(self, XB, Z, XA=None, math: str = "f32"):
+        """X^A = X^B + S V^T Z with X^B/X^A in their own type and the product
+        on `math` (enkf_analysis_ex)."""
+        xdt = _dtype_code(XB)
+        pXB, ldx = _mat(XB, "XB", xdt)
+        pZ, ldz = _mat(Z, "Z", self.dtype)
+        if XA is None:
+            XA = colmajor(XB.shape[0], XB.shape[1], XB.dtype, XB.device)
+        pXA, ldxa = _mat(XA, "XA", xdt)
+        _check(lib().enkf_analysis_ex(self._handle, XB.shape[0], xdt, MATH[math], pXB, ldx, pZ, ldz, pXA, ldxa),
+               "enkf_analysis_ex")
         return XA
 
     def info(self):

@@ -51,8 +51,8 @@ struct Plan {
   enkf_status create(const enkf_sm_desc& d, const double* r, const void* V, int64_t ldv, hipStream_t s);
   enkf_status factor();
   enkf_status solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, enkf_sm_info* info);
-  enkf_status analysis(int64_t n_state, const void* XB, int64_t ldx, const void* Z, int64_t ldz, void* XA,
-                       int64_t ldxa);
+  enkf_status analysis(int64_t n_state, enkf_dtype x_dtype, enkf_math math, const void* XB, int64_t ldx,
+                       const void* Z, int64_t ldz, void* XA, int64_t ldxa);
   enkf_status get_info(enkf_sm_info* info);
   enkf_status get_pivots(double* gamma_host, int32_t* perm_host);
   enkf_status read_status(unsigned* st);

@@ -471,8 +471,8 @@ enkf_status Plan::solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t l
   return ENKF_SUCCESS;
 }
 
-enkf_status Plan::analysis(int64_t n_state, const void* XB, int64_t ldx, const void* Z, int64_t ldz, void* XA,
-                           int64_t ldxa) {
+enkf_status Plan::analysis(int64_t n_state, enkf_dtype x_dtype, enkf_math math, const void* XB, int64_t ldx,
+                           const void* Z, int64_t ldz, void* XA, int64_t ldxa) {
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
   {
@@ -493,8 +493,10 @@ enkf_status Plan::analysis(int64_t n_state, const void* XB, int64_t ldx, const v
   a.ldc = ldx;
   a.Cout = XA;
   a.ldo = ldxa;
-  TimedLaunch tl(&timing, stream, KC_ANALYSIS, 2.0 * (double)n_state * N * es, 2.0 * (double)n_state * N * N);
-  return launch_nn(desc.dtype, NN_ANALYSIS, a, stream);
+  const size_t xes = dtype_size(x_dtype);
+  TimedLaunch tl(&timing, stream, KC_ANALYSIS, 2.0 * (double)n_state * N * xes, 2.0 * (double)n_state * N * N);
+  if (math == ENKF_MATH_F64 || math == ENKF_MATH_F32) return launch_nn(x_dtype, NN_ANALYSIS, a, stream);
+  return launch_nn_lowp(math, NN_ANALYSIS, a, stream);
 }
 
 enkf_status Plan::get_info(enkf_sm_info* info) {

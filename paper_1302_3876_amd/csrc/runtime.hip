@@ -189,20 +189,41 @@ enkf_status enkf_sm_solve(enkf_sm_plan plan, int32_t nrhs, const void* D, int64_
   return p->solve(nrhs, D, ldd, Z, ldz, info);
 }
 
-enkf_status enkf_analysis(enkf_sm_plan plan, int64_t n_state, const void* XB, int64_t ldx, const void* Z, int64_t ldz,
-                          void* XA, int64_t ldxa) {
-  if (!plan) return fail(ENKF_ERR_INVALID_ARG, "analysis: plan is NULL");
-  Plan* p = reinterpret_cast<Plan*>(plan);
+static enkf_status analysis_checks(Plan* p, int64_t n_state, enkf_dtype x_dtype, const void* XB, int64_t ldx,
+                                   const void* Z, int64_t ldz, void* XA, int64_t ldxa) {
   if (n_state < 1) return fail(ENKF_ERR_INVALID_ARG, "analysis: n_state must be >= 1");
   if (p->desc.n_ens < 2) return fail(ENKF_ERR_INVALID_ARG, "analysis: n_ens must be >= 2");
   if (!XB || !Z || !XA) return fail(ENKF_ERR_INVALID_ARG, "analysis: NULL pointer");
   if (ldx < n_state || ldxa < n_state || ldz < p->desc.n_obs)
     return fail(ENKF_ERR_INVALID_ARG, "analysis: leading dimension too small");
-  const size_t es = dtype_size(p->desc.dtype);
+  const size_t es = dtype_size(x_dtype);
   const uintptr_t xb0 = (uintptr_t)XB, xb1 = xb0 + ((size_t)ldx * (p->desc.n_ens - 1) + n_state) * es;
   const uintptr_t xa0 = (uintptr_t)XA, xa1 = xa0 + ((size_t)ldxa * (p->desc.n_ens - 1) + n_state) * es;
   if (xa0 < xb1 && xb0 < xa1) return fail(ENKF_ERR_INVALID_ARG, "analysis: XA overlaps XB");
-  return p->analysis(n_state, XB, ldx, Z, ldz, XA, ldxa);
+  return ENKF_SUCCESS;
+}
+
+enkf_status enkf_analysis(enkf_sm_plan plan, int64_t n_state, const void* XB, int64_t ldx, const void* Z, int64_t ldz,
+                          void* XA, int64_t ldxa) {
+  if (!plan) return fail(ENKF_ERR_INVALID_ARG, "analysis: plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  enkf_status st = analysis_checks(p, n_state, p->desc.dtype, XB, ldx, Z, ldz, XA, ldxa);
+  if (st != ENKF_SUCCESS) return st;
+  const enkf_math math = p->desc.dtype == ENKF_F64 ? ENKF_MATH_F64 : ENKF_MATH_F32;
+  return p->analysis(n_state, p->desc.dtype, math, XB, ldx, Z, ldz, XA, ldxa);
+}
+
+enkf_status enkf_analysis_ex(enkf_sm_plan plan, int64_t n_state, enkf_dtype x_dtype, enkf_math math, const void* XB,
+                             int64_t ldx, const void* Z, int64_t ldz, void* XA, int64_t ldxa) {
+  if (!plan) return fail(ENKF_ERR_INVALID_ARG, "analysis: plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (x_dtype != ENKF_F64 && x_dtype != ENKF_F32) return fail(ENKF_ERR_INVALID_ARG, "analysis: unknown x_dtype");
+  if (math < ENKF_MATH_F64 || math > ENKF_MATH_F16X2) return fail(ENKF_ERR_INVALID_ARG, "analysis: unknown math");
+  if ((x_dtype == ENKF_F64) != (math == ENKF_MATH_F64))
+    return fail(ENKF_ERR_INVALID_ARG, "analysis: FP64 ensembles take FP64 products; FP32 ensembles the others");
+  enkf_status st = analysis_checks(p, n_state, x_dtype, XB, ldx, Z, ldz, XA, ldxa);
+  if (st != ENKF_SUCCESS) return st;
+  return p->analysis(n_state, x_dtype, math, XB, ldx, Z, ldz, XA, ldxa);
 }
 
 enkf_status enkf_sm_get_info(enkf_sm_plan plan, enkf_sm_info* info) {

@@ -116,3 +116,23 @@ def test_mixed_split_forms_reach_gate_on_c3_like_data(math, maxit):
     torch.cuda.synchronize()
     print(math, info, flush=True)
     assert info["rel_residual"] <= 1e-10
+
+
+@pytest.mark.parametrize("math,tol", [("f32", 2e-5), ("bf16x3", 2e-5), ("f16x2", 2e-5), ("bf16", 2e-2), ("f16", 5e-3)])
+def test_analysis_ex_fp32_ensemble(math, tol):
+    """The analysis update on an FP32 ensemble with FP32/narrow matrix-core
+    inputs, against the FP64 oracle on the same (FP32-rounded) ensemble."""
+    import torch
+    pk = _pk()
+    w = synth.c2(n_state=131072, n_ens=96)
+    XB32 = w.XB.astype(np.float32).astype(np.float64)
+    E32 = w.E.astype(np.float32).astype(np.float64)
+    Vo, Do = oracle.build_vd(XB32, w.obs_idx, w.y, E32)
+    plan = pk.Plan(dev(w.r), dev(Vo), algo="blocked")
+    Z = plan.solve(dev(Do))
+    XA = plan.analysis_ex(dev(XB32, torch.float32), Z, math=math)
+    torch.cuda.synchronize()
+    XAo = oracle.analysis(XB32, Vo, oracle.sm_solve(w.r, Vo, Do)["Z"])
+    err = rel(host(XA) - XB32, XAo - XB32)
+    print(math, err, flush=True)
+    assert err < tol
