@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--block", type=int, default=0, help="panel width of the blocked forms (0: automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer 4 times (the known-size kernel that scales the HBM "
+                         "byte counters) and exit")
     return ap.parse_args()
 
 
@@ -338,6 +341,16 @@ def main():
               "sharding across GPUs is described in DESIGN.md but not built. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "launches": 4}), flush=True)
+        return
 
     import paper_1302_3876_amd as pk
     import synth

@@ -18,6 +18,7 @@ struct NnArgs {
   void* Cout; int64_t ldo;           // UPDATE: X (same as Cin); ANALYSIS: XA; RESIDUAL: rho
   const void* Din; int64_t ldd;      // RESIDUAL: D
   const double* r;                   // RESIDUAL: diag(R)
+  void* bws;                         // workspace: Bm converted (nn_bt_bytes(K, m) bytes)
   int64_t n_row_tiles;               // set by the launcher
   int n_col_tiles;                   // set by the launcher
 };
@@ -29,6 +30,9 @@ enkf_status launch_tn(enkf_dtype dt, int64_t n, int a, int m, const void* A, int
                       double* G, int64_t ldg, double* partial, hipStream_t s);
 
 enkf_status launch_nn(enkf_dtype dt, int mode, NnArgs p, hipStream_t s);
+// Leading dimension and size of the converted right factor of an nn product.
+int nn_bt_ld(int K);
+size_t nn_bt_bytes(int K, int m);
 // G (a x m, ldg) = sum over `chunks` partials of a x m (fixed order).
 enkf_status launch_partial_sum(int a, int m, int64_t chunks, const double* partial, double* G, int64_t ldg,
                                hipStream_t s);

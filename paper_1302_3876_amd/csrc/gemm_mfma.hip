@@ -13,8 +13,9 @@
 //      Bm is FP64 (it comes from the FP64 panel factorisation or from the
 //      FP64 products) and is rounded to the MFMA input type when staged.
 //
-// Both kernels: 256 threads (4 waves, 2 x 2), 128 x 128 output tiles (each
-// wave 64 x 64 = 4 x 4 MFMA tiles; nn in FP64: 128 x 64), inner-dimension stages of KC staged in LDS
+// Both kernels: 256 threads (4 waves, 2 x 2); tn uses 128 x 128 output tiles
+// (each wave 64 x 64 = 4 x 4 MFMA tiles), nn 64 x 128 when the product has at
+// most 128 columns, else 128 x 64 (FP64) or 128 x 128 (FP32); inner-dimension stages of KC staged in LDS
 // through registers with 16-byte global loads, double-buffered so the next
 // stage's loads are in flight while the matrix cores work on the current one.
 // tn stages both operands k-contiguous ([col][k], padded: conflict-free MFMA
@@ -208,60 +209,77 @@ __global__ __launch_bounds__(256) void partial_sum_kernel(int a, int m, int64_t 
 }
 
 // ---------------------------------------------------------------- nn
-// Column tile of nn: 64 in FP64 (keeps the accumulators at 32 doubles per
-// lane, so two waves fit per SIMD), 128 in FP32.
-template <typename T> constexpr int nn_tc() { return sizeof(T) == 8 ? 64 : 128; }
+// B = scale * Bm converted once per call to the storage type, K padded to a
+// multiple of 16 with zeros (so the kernel stages B without bounds checks on
+// k and with 16-byte loads).
+template <typename T>
+__global__ __launch_bounds__(256) void convert_b_kernel(int K, int m, const double* __restrict__ Bm, int64_t ldb,
+                                                        double scale, T* __restrict__ Bt, int ldbt) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)ldbt * m) return;
+  const int k = (int)(e % ldbt), j = (int)(e / ldbt);
+  Bt[e] = (k < K) ? (T)(scale * Bm[k + (int64_t)j * ldb]) : T(0);
+}
 
-// Stage layout: As[k][row] (row stride TILE+1), Bs[k][col] (stride TC+1).
-template <typename T, int MODE>
-__global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, bool vec) {
+// Stage layout: As[k][row] (row stride TR+1), Bs[k][col] (stride TC+1).
+// Waves 2 x 2: wave (w/2, w%2) owns TC/2 columns x TR/2 rows.
+template <typename T, int MODE, int TR, int TC>
+__global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ Bt, int ldbt, bool vec) {
   typedef typename MfOf<T>::type MF;
   typedef typename V16<T>::type vt;
   constexpr int W = V16<T>::W;
   constexpr int KC = kc_of<T>();
-  constexpr int TC = nn_tc<T>();
   constexpr int CI = TC / 32;                     // MFMA column tiles per wave
-  constexpr int LDR = TILE + 1;
+  constexpr int RJ = TR / 32;                     // MFMA row tiles per wave
+  constexpr int LDR = TR + 1;
   constexpr int LDC = TC + 1;
-  constexpr int ROWCH = TILE / W;                 // 16-byte loads per k column of the A tile
-  constexpr int A_PASSES = (KC * ROWCH) / NT;     // passes to load KC columns of TILE rows
-  constexpr int B_PER_T = (KC * TC) / NT;         // B elements per thread per stage
+  constexpr int ROWCH = TR / W;                   // 16-byte loads per k column of the A tile
+  constexpr int A_PASSES = (KC * ROWCH) / NT;
+  constexpr int BCH = KC / W;                     // 16-byte loads per column of the B stage
+  constexpr int B_PASSES = (TC * BCH) / NT;
+  static_assert(A_PASSES >= 1 && B_PASSES >= 1, "tile too small for the block");
   __shared__ T As[2][KC * LDR];
   __shared__ T Bs[2][KC * LDC];
-  __shared__ double mean[TILE];
+  __shared__ double mean[TR];
   int64_t rt;
   int ct;
   xcd_tile_map(blockIdx.x, p.n_row_tiles, p.n_col_tiles, &rt, &ct);
   if (rt >= p.n_row_tiles) return;
-  const int64_t row0 = rt * TILE;
+  const int64_t row0 = rt * TR;
   const int col0 = ct * TC;
   const T* __restrict__ A = static_cast<const T*>(p.A);
   const int t = threadIdx.x, l = t % kWave, w = t / kWave;
-  const int c_off = (w / 2) * (TC / 2), r_off = (w % 2) * 64;
+  const int c_off = (w / 2) * (TC / 2), r_off = (w % 2) * (TR / 2);
   const int64_t rlim = p.n;
 
   if constexpr (MODE == NN_ANALYSIS) {
-    // row means of the block's rows (two threads per row, fixed order)
-    __shared__ double part[2][TILE];
-    const int rr = t % TILE, q = t / TILE;
+    // row means of the block's rows (fixed order)
+    constexpr int Q = NT / TR;
+    __shared__ double part[Q][TR];
+    const int rr = t % TR, q = t / TR;
     const int64_t row = row0 + rr;
     double s = 0.0;
     if (row < p.n)
-      for (int j = q; j < p.K; j += 2) s += (double)A[row + (int64_t)j * p.lda];
+      for (int j = q; j < p.K; j += Q) s += (double)A[row + (int64_t)j * p.lda];
     part[q][rr] = s;
     __syncthreads();
-    if (t < TILE) mean[t] = (part[0][t] + part[1][t]) / (double)p.K;
+    if (t < TR) {
+      double tot = 0.0;
+#pragma unroll
+      for (int z = 0; z < Q; ++z) tot += part[z][t];
+      mean[t] = tot / (double)p.K;
+    }
     __syncthreads();
   }
 
-  typename MF::acc_t acc[CI][4];
+  typename MF::acc_t acc[CI][RJ];
 #pragma unroll
   for (int i = 0; i < CI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = MF::zero();
+    for (int j = 0; j < RJ; ++j) acc[i][j] = MF::zero();
 
   vt areg[A_PASSES];
-  T breg[B_PER_T];
+  vt breg[B_PASSES];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < A_PASSES; ++q) {
@@ -275,11 +293,15 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, bool vec) {
       }
     }
 #pragma unroll
-    for (int q = 0; q < B_PER_T; ++q) {
+    for (int q = 0; q < B_PASSES; ++q) {
       const int e = q * NT + t;
-      const int kk = e % KC, cc = e / KC;
-      breg[q] = (k0 + kk < p.K && col0 + cc < p.m) ? (T)(p.scale * p.Bm[(k0 + kk) + (int64_t)(col0 + cc) * p.ldb])
-                                                   : T(0);
+      const int cc = e / BCH, kk = (e % BCH) * W;
+      if (col0 + cc < p.m && k0 + kk < ldbt) {
+        breg[q] = *reinterpret_cast<const vt*>(Bt + (int64_t)(col0 + cc) * ldbt + k0 + kk);
+      } else {
+#pragma unroll
+        for (int x = 0; x < W; ++x) breg[q][x] = T(0);
+      }
     }
   };
   auto stash = [&](int buf) {
@@ -296,10 +318,11 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, bool vec) {
       }
     }
 #pragma unroll
-    for (int q = 0; q < B_PER_T; ++q) {
+    for (int q = 0; q < B_PASSES; ++q) {
       const int e = q * NT + t;
-      const int kk = e % KC, cc = e / KC;
-      Bs[buf][kk * LDC + cc] = breg[q];
+      const int cc = e / BCH, kk = (e % BCH) * W;
+#pragma unroll
+      for (int x = 0; x < W; ++x) Bs[buf][(kk + x) * LDC + cc] = breg[q][x];
     }
   };
 
@@ -312,15 +335,15 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, bool vec) {
     if (more) fetch(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += MF::KSTEP) {
-      T cop[CI], rop[4];
+      T cop[CI], rop[RJ];
 #pragma unroll
       for (int i = 0; i < CI; ++i) cop[i] = Bs[buf][(kk + l / 16) * LDC + c_off + 16 * i + l % 16];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) rop[j] = As[buf][(kk + l / 16) * LDR + r_off + 16 * j + l % 16];
+      for (int j = 0; j < RJ; ++j) rop[j] = As[buf][(kk + l / 16) * LDR + r_off + 16 * j + l % 16];
 #pragma unroll
       for (int i = 0; i < CI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = MF::mma(cop[i], rop[j], acc[i][j]);
+        for (int j = 0; j < RJ; ++j) acc[i][j] = MF::mma(cop[i], rop[j], acc[i][j]);
     }
     if (more) stash(buf ^ 1);
     __syncthreads();
@@ -332,7 +355,7 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, bool vec) {
 #pragma unroll
   for (int i = 0; i < CI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < RJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = col0 + c_off + 16 * i + MF::row(l, r);
@@ -401,28 +424,53 @@ enkf_status launch_partial_sum(int a, int m, int64_t chunks, const double* parti
   return ENKF_SUCCESS;
 }
 
-enkf_status launch_nn(enkf_dtype dt, int mode, NnArgs p, hipStream_t s) {
-  if (p.n <= 0 || p.m <= 0) return ENKF_SUCCESS;
-  const int tc = dt == ENKF_F64 ? nn_tc<double>() : nn_tc<float>();
-  p.n_row_tiles = (p.n + TILE - 1) / TILE;
-  p.n_col_tiles = (p.m + tc - 1) / tc;
+int nn_bt_ld(int K) { return (K + 15) / 16 * 16; }
+
+size_t nn_bt_bytes(int K, int m) { return sizeof(double) * (size_t)nn_bt_ld(K) * (size_t)m; }
+
+namespace {
+
+template <typename T, int MODE, int TR, int TC>
+enkf_status nn_go(NnArgs p, const T* Bt, int ldbt, bool vec, hipStream_t s) {
+  p.n_row_tiles = (p.n + TR - 1) / TR;
+  p.n_col_tiles = (p.m + TC - 1) / TC;
   const int64_t groups = (p.n_row_tiles + 7) / 8;
   const int64_t blocks = groups * 8 * p.n_col_tiles;
   if (blocks > 0x7fffffff) return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
-  const unsigned g = (unsigned)blocks;
-  const size_t es = dt == ENKF_F64 ? 8 : 4;
-  const bool vec = aligned16(p.A, p.lda, es);
-  if (dt == ENKF_F64) {
-    if (mode == NN_UPDATE) nn_kernel<double, NN_UPDATE><<<g, NT, 0, s>>>(p, vec);
-    else if (mode == NN_ANALYSIS) nn_kernel<double, NN_ANALYSIS><<<g, NT, 0, s>>>(p, vec);
-    else nn_kernel<double, NN_RESIDUAL><<<g, NT, 0, s>>>(p, vec);
-  } else {
-    if (mode == NN_UPDATE) nn_kernel<float, NN_UPDATE><<<g, NT, 0, s>>>(p, vec);
-    else if (mode == NN_ANALYSIS) nn_kernel<float, NN_ANALYSIS><<<g, NT, 0, s>>>(p, vec);
-    else nn_kernel<float, NN_RESIDUAL><<<g, NT, 0, s>>>(p, vec);
-  }
+  nn_kernel<T, MODE, TR, TC><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbt, vec);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
+}
+
+// Tile choice: one column tile of 128 when m <= 128 (64 rows), else
+// 128 rows x 64 (FP64) or 128 (FP32) columns.
+template <typename T, int MODE>
+enkf_status nn_pick(NnArgs p, const T* Bt, int ldbt, bool vec, hipStream_t s) {
+  if (p.m <= 128) return nn_go<T, MODE, 64, 128>(p, Bt, ldbt, vec, s);
+  if constexpr (sizeof(T) == 8) return nn_go<T, MODE, 128, 64>(p, Bt, ldbt, vec, s);
+  else return nn_go<T, MODE, 128, 128>(p, Bt, ldbt, vec, s);
+}
+
+template <typename T>
+enkf_status nn_typed(int mode, NnArgs p, hipStream_t s) {
+  T* Bt = static_cast<T*>(p.bws);
+  const int ldbt = nn_bt_ld(p.K);
+  const int64_t total = (int64_t)ldbt * p.m;
+  convert_b_kernel<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(p.K, p.m, p.Bm, p.ldb, p.scale, Bt, ldbt);
+  ENKF_HIP_CHECK(hipGetLastError());
+  const bool vec = aligned16(p.A, p.lda, sizeof(T));
+  if (mode == NN_UPDATE) return nn_pick<T, NN_UPDATE>(p, Bt, ldbt, vec, s);
+  if (mode == NN_ANALYSIS) return nn_pick<T, NN_ANALYSIS>(p, Bt, ldbt, vec, s);
+  return nn_pick<T, NN_RESIDUAL>(p, Bt, ldbt, vec, s);
+}
+
+}  // namespace
+
+enkf_status launch_nn(enkf_dtype dt, int mode, NnArgs p, hipStream_t s) {
+  if (p.n <= 0 || p.m <= 0) return ENKF_SUCCESS;
+  if (!p.bws) return fail(ENKF_ERR_INVALID_ARG, "nn product: no workspace for the converted right factor");
+  if (dt == ENKF_F64) return nn_typed<double>(mode, p, s);
+  return nn_typed<float>(mode, p, s);
 }
 
 }  // namespace enkf

@@ -29,6 +29,7 @@ struct Plan {
   unsigned* status = nullptr;   // device status word
   double* G = nullptr;          // N x N products V^T Z (analysis), N x nrhs (residual)
   double* tn_part = nullptr;    // split-K partials of the tn products
+  char* Bt = nullptr;           // converted right factor of the nn products
   // blocked
   int block = 0;                // panel width b
   int npanel = 0;

@@ -97,6 +97,8 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   if (mixed)
     for (int m = 1; m <= max_nrhs; ++m) tnp = std::max(tnp, tn_partial_elems(n, N, m));
   const size_t oTn = take(sizeof(double) * (size_t)tnp);
+  // right factor of an nn product, converted: inner dimension <= N, columns <= mcols
+  const size_t oBt = take(nn_bt_bytes(N, mcols));
   size_t oP0 = 0, oP1 = 0, oMinv = 0, oPbuf = 0, oQbuf = 0, oVw = 0, oZw = 0, oRho = 0, oNorm = 0;
   if (!blocked) {
     const size_t part_elems = (size_t)level_row_blocks(d.dtype, 1, n) * mcols;
@@ -124,6 +126,7 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   status = reinterpret_cast<unsigned*>(ws + oStat);
   G = reinterpret_cast<double*>(ws + oG);
   tn_part = reinterpret_cast<double*>(ws + oTn);
+  Bt = ws + oBt;
   if (!blocked) {
     part[0] = reinterpret_cast<double*>(ws + oP0);
     part[1] = reinterpret_cast<double*>(ws + oP1);
@@ -294,6 +297,7 @@ enkf_status Plan::factor_blocked() {
     }
     if (mrest > 0) {
       NnArgs a{};
+    a.bws = Bt;
       a.n = n;
       a.K = bl;
       a.m = mrest;
@@ -343,6 +347,7 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
       if (st != ENKF_SUCCESS) return st;
     }
     NnArgs a{};
+    a.bws = Bt;
     a.n = n;
     a.K = bl;
     a.m = nrhs;
@@ -388,6 +393,7 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
     }
     {
       NnArgs a{};
+    a.bws = Bt;
       a.n = n;
       a.K = N;
       a.m = nrhs;
@@ -481,6 +487,7 @@ enkf_status Plan::analysis(int64_t n_state, enkf_dtype x_dtype, enkf_math math, 
     if (st != ENKF_SUCCESS) return st;
   }
   NnArgs a{};
+    a.bws = Bt;
   a.n = n_state;
   a.K = N;
   a.m = N;
