@@ -30,8 +30,7 @@ enkf_status launch_tn(enkf_dtype dt, int64_t n, int a, int m, const void* A, int
                       double* G, int64_t ldg, double* partial, hipStream_t s);
 
 enkf_status launch_nn(enkf_dtype dt, int mode, NnArgs p, hipStream_t s);
-// Leading dimension and size of the converted right factor of an nn product.
-int nn_bt_ld(int K);
+// Workspace bytes of the converted right factor of an nn product.
 size_t nn_bt_bytes(int K, int m);
 // G (a x m, ldg) = sum over `chunks` partials of a x m (fixed order).
 enkf_status launch_partial_sum(int a, int m, int64_t chunks, const double* partial, double* G, int64_t ldg,

@@ -43,76 +43,104 @@ template <> struct V16<float> { static constexpr int W = 4; typedef float type _
 
 template <typename T> constexpr int kc_of() { return sizeof(T) == 8 ? 16 : 32; }
 
-// Load W consecutive elements of a column starting at row `row` (rows < rlim
-// only; others are zero). `vec` says the 16-byte path is aligned.
-template <typename T>
-__device__ __forceinline__ typename V16<T>::type load_col_vec(const T* __restrict__ p, int64_t row, int64_t rlim,
-                                                              bool vec) {
+// Staged global loads are branch-free: an index outside the valid range is
+// replaced by a valid one, and where the value matters the staged value is
+// replaced by zero when it is written to LDS (after the matrix-core work of
+// the current stage, so the loads stay in flight meanwhile). Branches around
+// loads, or selects right after them, make the compiler wait for every load
+// in flight and serialise the prefetch.
+// VEC: 16-byte loads; the launcher guarantees 16-byte aligned columns and a
+// row limit that is a multiple of W, so a vector is wholly inside or wholly
+// outside the valid rows.
+template <typename T, bool VEC>
+__device__ __forceinline__ typename V16<T>::type load_rows(const T* __restrict__ col, int64_t row, int64_t rlim) {
   typedef typename V16<T>::type vt;
   constexpr int W = V16<T>::W;
   vt v;
-  if (vec && row + W <= rlim) {
-    v = *reinterpret_cast<const vt*>(p + row);
+  if constexpr (VEC) {
+    v = *reinterpret_cast<const vt*>(col + (row < rlim ? row : 0));
   } else {
 #pragma unroll
-    for (int e = 0; e < W; ++e) v[e] = (row + e < rlim) ? p[row + e] : T(0);
+    for (int e = 0; e < W; ++e) v[e] = col[row + e < rlim ? row + e : 0];
   }
   return v;
 }
 
-// ---------------------------------------------------------------- tn
-// Stage layout: S[col][k], col in [0, 2*TILE) (A columns then B columns),
-// k in [0, KC), row stride KC+1.
+// Zero the elements of v at rows >= rlim.
 template <typename T>
-__global__ __launch_bounds__(NT) void tn_partial_kernel(int64_t n, int a, int m, const T* __restrict__ A, int64_t lda,
+__device__ __forceinline__ typename V16<T>::type zero_past(typename V16<T>::type v, int64_t row, int64_t rlim) {
+  constexpr int W = V16<T>::W;
+#pragma unroll
+  for (int e = 0; e < W; ++e) v[e] = row + e < rlim ? v[e] : T(0);
+  return v;
+}
+
+// ---------------------------------------------------------------- tn
+// Stage layout: S[col][k], col in [0, TA + TILE) (A columns then B columns),
+// k in [0, KC), row stride LDK (FP32: KC+4, 16-byte rows, conflict-free MFMA
+// reads; FP64: KC+1). One LDS buffer: the next stage is prefetched into
+// registers while the matrix cores work on the current one.
+template <typename T> constexpr int tn_ldk() { return sizeof(T) == 8 ? kc_of<T>() + 1 : kc_of<T>() + 4; }
+
+// 2 x WA waves, wave tile 64 (m) x 32 (a) = 4 x 2 MFMA tiles; block tile
+// 128 (m) x TA = 32*WA (a). FP64: WA = 4 (two 8-wave blocks per CU); FP32:
+// WA = 2 (its FP64 flush accumulators need more registers: three 4-wave
+// blocks per CU).
+template <typename T> constexpr int tn_wa() { return sizeof(T) == 8 ? 4 : 2; }
+
+template <typename T, bool VEC, int WA>
+__global__ __launch_bounds__(128 * WA, WA == 2 ? 3 : 4) void tn_partial_kernel(int64_t n, int a, int m, const T* __restrict__ A, int64_t lda,
                                                         const T* __restrict__ B, int64_t ldb,
                                                         double* __restrict__ partial, int64_t rows_per_chunk,
-                                                        int tiles_m, bool vec) {
+                                                        int tiles_m) {
   typedef typename MfOf<T>::type MF;
   typedef typename V16<T>::type vt;
   constexpr int W = V16<T>::W;
   constexpr int KC = kc_of<T>();
-  constexpr int LDK = KC + 1;
-  constexpr int COLS = 2 * TILE;
+  constexpr int LDK = tn_ldk<T>();
+  constexpr int TN_NT = 128 * WA;
+  constexpr int TA = 32 * WA;
+  constexpr int COLS = TA + TILE;
   constexpr int PER_COL = KC / W;                 // 16-byte loads per column per stage
-  constexpr int COLS_PER_PASS = NT / PER_COL;
+  constexpr int COLS_PER_PASS = TN_NT / PER_COL;
   constexpr int PASSES = COLS / COLS_PER_PASS;
-  __shared__ T S[2][COLS * LDK];
+  __shared__ T S[COLS * LDK];
 
   const int ta = blockIdx.y / tiles_m, tm = blockIdx.y % tiles_m;
-  const int a0 = ta * TILE, m0 = tm * TILE;
+  const int a0 = ta * TA, m0 = tm * TILE;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
   const int64_t r1 = min(n, r0 + rows_per_chunk);
   const int t = threadIdx.x, l = t % kWave, w = t / kWave;
-  const int m_off = (w / 2) * 64, a_off = (w % 2) * 64;
+  const int m_off = (w / WA) * 64, a_off = (w % WA) * 32;
   const int lc = t / PER_COL, lk = (t % PER_COL) * W;
 
-  // column pointers of this thread's staged columns (nullptr: outside)
+  // this thread's staged columns; a column outside the operand is replaced by
+  // its last column (it only feeds outputs that are not stored)
   const T* cp[PASSES];
 #pragma unroll
   for (int p = 0; p < PASSES; ++p) {
     const int c = p * COLS_PER_PASS + lc;
-    if (c < TILE) cp[p] = (a0 + c < a) ? A + (int64_t)(a0 + c) * lda : nullptr;
-    else cp[p] = (m0 + c - TILE < m) ? B + (int64_t)(m0 + c - TILE) * ldb : nullptr;
+    if (c < TA) cp[p] = A + (int64_t)min(a0 + c, a - 1) * lda;
+    else cp[p] = B + (int64_t)min(m0 + c - TA, m - 1) * ldb;
   }
 
-  typename MF::acc_t acc[4][4];
+  typename MF::acc_t acc[4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = MF::zero();
+    for (int j = 0; j < 2; ++j) acc[i][j] = MF::zero();
   // FP32 accumulators are emptied into FP64 ones every kFlush stages, so no
   // FP32 sum runs over more than kFlush*KC rows (long FP32 sums over the
   // observations would otherwise dominate the error of the mixed solve).
   constexpr bool kWide = sizeof(T) == 4;
   constexpr int kFlush = 2;
-  double wide[kWide ? 4 : 1][kWide ? 4 : 1][kWide ? 4 : 1] = {};
+  double wide[kWide ? 4 : 1][kWide ? 2 : 1][kWide ? 4 : 1] = {};
   auto flush = [&]() {
     if constexpr (kWide) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) wide[i][j][r] += (double)acc[i][j][r];
           acc[i][j] = MF::zero();
@@ -121,56 +149,61 @@ __global__ __launch_bounds__(NT) void tn_partial_kernel(int64_t n, int a, int m,
   };
 
   vt reg[PASSES];
+  // fetch is unconditional (past the chunk it reads row 0 again, discarded)
   auto fetch = [&](int64_t rs) {
 #pragma unroll
-    for (int p = 0; p < PASSES; ++p) {
-      if (cp[p]) reg[p] = load_col_vec<T>(cp[p], rs + lk, r1, vec);
-      else {
+    for (int p = 0; p < PASSES; ++p) reg[p] = load_rows<T, VEC>(cp[p], rs + lk, r1);
+  };
+  auto stash = [&](int64_t rs) {
 #pragma unroll
-        for (int e = 0; e < W; ++e) reg[p][e] = T(0);
+    for (int p = 0; p < PASSES; ++p) {
+      T* dst = &S[(p * COLS_PER_PASS + lc) * LDK + lk];
+      const vt v = zero_past<T>(reg[p], rs + lk, r1);
+      if constexpr (LDK % W == 0) {
+        *reinterpret_cast<vt*>(dst) = v;
+      } else {
+#pragma unroll
+        for (int e = 0; e < W; ++e) dst[e] = v[e];
       }
     }
   };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int p = 0; p < PASSES; ++p) {
-      T* dst = &S[buf][(p * COLS_PER_PASS + lc) * LDK + lk];
-#pragma unroll
-      for (int e = 0; e < W; ++e) dst[e] = reg[p][e];
-    }
-  };
 
-  int buf = 0;
   if (r0 < r1) {
     fetch(r0);
-    stash(0);
+    stash(r0);
   }
   __syncthreads();
   int stage = 0;
   for (int64_t rs = r0; rs < r1; rs += KC) {
-    const bool more = rs + KC < r1;
-    if (more) fetch(rs + KC);
-    const T* Sa = &S[buf][0];
-    const T* Sb = &S[buf][TILE * LDK];
+    fetch(rs + KC);
+    // keep the prefetch ahead of the matrix-core work (the scheduler would
+    // otherwise sink the loads next to their first use)
+    __builtin_amdgcn_sched_barrier(0);
+    const T* Sa = &S[0];
+    const T* Sb = &S[TA * LDK];
 #pragma unroll
     for (int kk = 0; kk < KC; kk += MF::KSTEP) {
-      T bop[4], aop[4];
+      T bop[4], aop[2];
 #pragma unroll
       for (int i = 0; i < 4; ++i) bop[i] = Sb[(m_off + 16 * i + l % 16) * LDK + kk + l / 16];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) aop[j] = Sa[(a_off + 16 * j + l % 16) * LDK + kk + l / 16];
+      for (int j = 0; j < 2; ++j) aop[j] = Sa[(a_off + 16 * j + l % 16) * LDK + kk + l / 16];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = MF::mma(bop[i], aop[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = MF::mma(bop[i], aop[j], acc[i][j]);
     }
-    if (more) stash(buf ^ 1);
     if (kWide && ++stage == kFlush) {
       flush();
       stage = 0;
     }
+    // unconditional (after the last stage it stages zeros): a conditional
+    // stash would let the compiler sink the prefetch into the condition; the
+    // scheduling barrier keeps the stash's use of the loads after the MFMAs
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
-    buf ^= 1;
+    stash(rs + KC);
+    __syncthreads();
   }
   flush();
   // acc[i][j] element (row = m index, col = a index)
@@ -178,7 +211,7 @@ __global__ __launch_bounds__(NT) void tn_partial_kernel(int64_t n, int a, int m,
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int mi = m0 + m_off + 16 * i + MF::row(l, r);
@@ -209,37 +242,40 @@ __global__ __launch_bounds__(256) void partial_sum_kernel(int a, int m, int64_t 
 }
 
 // ---------------------------------------------------------------- nn
-// B = scale * Bm converted once per call to the storage type, K padded to a
-// multiple of 16 with zeros (so the kernel stages B without bounds checks on
-// k and with 16-byte loads).
+// The right factor, scale * Bm, is converted once per call to the storage
+// type and laid out row-major, Bt[k * ldbc + j], with zero padding to
+// nn_bt_rows(K) rows and nn_bt_cols(m) columns: every stage of every tile
+// reads it without bounds checks, 16 bytes at a time.
 template <typename T>
 __global__ __launch_bounds__(256) void convert_b_kernel(int K, int m, const double* __restrict__ Bm, int64_t ldb,
-                                                        double scale, T* __restrict__ Bt, int ldbt) {
+                                                        double scale, T* __restrict__ Bt, int rows, int ldbc) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)ldbt * m) return;
-  const int k = (int)(e % ldbt), j = (int)(e / ldbt);
-  Bt[e] = (k < K) ? (T)(scale * Bm[k + (int64_t)j * ldb]) : T(0);
+  if (e >= (int64_t)rows * ldbc) return;
+  const int j = (int)(e % ldbc), k = (int)(e / ldbc);
+  Bt[e] = (k < K && j < m) ? (T)(scale * Bm[k + (int64_t)j * ldb]) : T(0);
 }
 
-// Stage layout: As[k][row] (row stride TR+1), Bs[k][col] (stride TC+1).
-// Waves 2 x 2: wave (w/2, w%2) owns TC/2 columns x TR/2 rows.
-template <typename T, int MODE, int TR, int TC>
-__global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ Bt, int ldbt, bool vec) {
+// Stage layout: As[k][row] (row stride TR+16), Bs[k][col] (stride TC+16):
+// 16-byte LDS writes along rows/columns, conflict-free MFMA operand reads.
+// Waves 2 x 2: wave (w/2, w%2) owns TC/2 columns x TR/2 rows. One LDS
+// buffer; the next stage is prefetched into registers.
+template <typename T, int MODE, int TR, int TC, bool VEC>
+__global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ Bt, int ldbc) {
   typedef typename MfOf<T>::type MF;
   typedef typename V16<T>::type vt;
   constexpr int W = V16<T>::W;
   constexpr int KC = kc_of<T>();
   constexpr int CI = TC / 32;                     // MFMA column tiles per wave
   constexpr int RJ = TR / 32;                     // MFMA row tiles per wave
-  constexpr int LDR = TR + 1;
-  constexpr int LDC = TC + 1;
-  constexpr int ROWCH = TR / W;                   // 16-byte loads per k column of the A tile
+  constexpr int LDR = TR + 16;
+  constexpr int LDC = TC + 16;
+  constexpr int ROWCH = TR / W;                   // 16-byte loads per k of the A tile
   constexpr int A_PASSES = (KC * ROWCH) / NT;
-  constexpr int BCH = KC / W;                     // 16-byte loads per column of the B stage
-  constexpr int B_PASSES = (TC * BCH) / NT;
+  constexpr int COLCH = TC / W;                   // 16-byte loads per k of the B stage
+  constexpr int B_PASSES = (KC * COLCH) / NT;
   static_assert(A_PASSES >= 1 && B_PASSES >= 1, "tile too small for the block");
-  __shared__ T As[2][KC * LDR];
-  __shared__ T Bs[2][KC * LDC];
+  __shared__ T As[KC * LDR];
+  __shared__ T Bs[KC * LDC];
   __shared__ double mean[TR];
   int64_t rt;
   int ct;
@@ -251,16 +287,27 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
   const int t = threadIdx.x, l = t % kWave, w = t / kWave;
   const int c_off = (w / 2) * (TC / 2), r_off = (w % 2) * (TR / 2);
   const int64_t rlim = p.n;
+  const int bt_rows = (p.K + 31) / 32 * 32;   // rows of Bt (nn_bt_rows)
 
   if constexpr (MODE == NN_ANALYSIS) {
-    // row means of the block's rows (fixed order)
+    // row means of the block's rows: NT/TR partial sums per row, each over a
+    // fixed subset of the columns, added in a fixed order
     constexpr int Q = NT / TR;
+    constexpr int U = 8;
     __shared__ double part[Q][TR];
     const int rr = t % TR, q = t / TR;
-    const int64_t row = row0 + rr;
+    const int64_t row = min(row0 + rr, rlim - 1);
+    const T* __restrict__ ar = A + row;
     double s = 0.0;
-    if (row < p.n)
-      for (int j = q; j < p.K; j += Q) s += (double)A[row + (int64_t)j * p.lda];
+    int j = q;
+    for (; j + (U - 1) * Q < p.K; j += U * Q) {
+      T x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = ar[(int64_t)(j + u * Q) * p.lda];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += (double)x[u];
+    }
+    for (; j < p.K; j += Q) s += (double)ar[(int64_t)j * p.lda];
     part[q][rr] = s;
     __syncthreads();
     if (t < TR) {
@@ -280,96 +327,106 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
 
   vt areg[A_PASSES];
   vt breg[B_PASSES];
+  // fetch is unconditional: a column index past K reads column K-1 (zeroed
+  // when staged; Bt is zero there as well); rows past n only feed outputs
+  // that are not stored
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < A_PASSES; ++q) {
       const int e = q * NT + t;
       const int kk = e / ROWCH, rc = (e % ROWCH) * W;
-      if (k0 + kk < p.K) {
-        areg[q] = load_col_vec<T>(A + (int64_t)(k0 + kk) * p.lda, row0 + rc, rlim, vec);
-      } else {
-#pragma unroll
-        for (int x = 0; x < W; ++x) areg[q][x] = T(0);
-      }
+      const int k = min(k0 + kk, p.K - 1);
+      areg[q] = load_rows<T, VEC>(A + (int64_t)k * p.lda, row0 + rc, rlim);
     }
 #pragma unroll
     for (int q = 0; q < B_PASSES; ++q) {
       const int e = q * NT + t;
-      const int cc = e / BCH, kk = (e % BCH) * W;
-      if (col0 + cc < p.m && k0 + kk < ldbt) {
-        breg[q] = *reinterpret_cast<const vt*>(Bt + (int64_t)(col0 + cc) * ldbt + k0 + kk);
-      } else {
-#pragma unroll
-        for (int x = 0; x < W; ++x) breg[q][x] = T(0);
-      }
+      const int kk = e / COLCH, cc = (e % COLCH) * W;
+      const int k = min(k0 + kk, bt_rows - 1);
+      breg[q] = *reinterpret_cast<const vt*>(Bt + (int64_t)k * ldbc + col0 + cc);
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < A_PASSES; ++q) {
       const int e = q * NT + t;
       const int kk = e / ROWCH, rc = (e % ROWCH) * W;
-      T* dst = &As[buf][kk * LDR + rc];
+      const bool kok = k0 + kk < p.K;
+      vt v = areg[q];
 #pragma unroll
       for (int x = 0; x < W; ++x) {
-        T v = areg[q][x];
-        if constexpr (MODE == NN_ANALYSIS) v = (T)((double)v - mean[rc + x]);
-        dst[x] = v;
+        if constexpr (MODE == NN_ANALYSIS) v[x] = (T)((double)v[x] - mean[rc + x]);
+        v[x] = kok ? v[x] : T(0);
       }
+      *reinterpret_cast<vt*>(&As[kk * LDR + rc]) = v;
     }
 #pragma unroll
     for (int q = 0; q < B_PASSES; ++q) {
       const int e = q * NT + t;
-      const int cc = e / BCH, kk = (e % BCH) * W;
-#pragma unroll
-      for (int x = 0; x < W; ++x) Bs[buf][(kk + x) * LDC + cc] = breg[q][x];
+      const int kk = e / COLCH, cc = (e % COLCH) * W;
+      *reinterpret_cast<vt*>(&Bs[kk * LDC + cc]) = breg[q];
     }
   };
 
-  int buf = 0;
   fetch(0);
   stash(0);
   __syncthreads();
   for (int k0 = 0; k0 < p.K; k0 += KC) {
-    const bool more = k0 + KC < p.K;
-    if (more) fetch(k0 + KC);
+    fetch(k0 + KC);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += MF::KSTEP) {
       T cop[CI], rop[RJ];
 #pragma unroll
-      for (int i = 0; i < CI; ++i) cop[i] = Bs[buf][(kk + l / 16) * LDC + c_off + 16 * i + l % 16];
+      for (int i = 0; i < CI; ++i) cop[i] = Bs[(kk + l / 16) * LDC + c_off + 16 * i + l % 16];
 #pragma unroll
-      for (int j = 0; j < RJ; ++j) rop[j] = As[buf][(kk + l / 16) * LDR + r_off + 16 * j + l % 16];
+      for (int j = 0; j < RJ; ++j) rop[j] = As[(kk + l / 16) * LDR + r_off + 16 * j + l % 16];
 #pragma unroll
       for (int i = 0; i < CI; ++i)
 #pragma unroll
         for (int j = 0; j < RJ; ++j) acc[i][j] = MF::mma(cop[i], rop[j], acc[i][j]);
     }
-    if (more) stash(buf ^ 1);
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
-    buf ^= 1;
+    stash(k0 + KC);
+    __syncthreads();
   }
-  // acc[i][j] element (row = output column, col = output row)
+  // acc[i][j] element (row = output column, col = output row). The inputs of
+  // the epilogue are loaded for all of the wave's outputs first (clamped
+  // indices, no branches), so their latencies overlap; stores are predicated.
   const T* __restrict__ Cin = static_cast<const T*>(p.Cin);
+  const T* __restrict__ Din = static_cast<const T*>(p.Din);
   T* __restrict__ Cout = static_cast<T*>(p.Cout);
 #pragma unroll
-  for (int i = 0; i < CI; ++i)
+  for (int i = 0; i < CI; ++i) {
+    T cin[RJ][4], din[RJ][4];
+    double rr[RJ];
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) {
+      const int64_t row = min(row0 + r_off + 16 * j + l % 16, rlim - 1);
+      if constexpr (MODE == NN_RESIDUAL) rr[j] = p.r[row];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = min(col0 + c_off + 16 * i + MF::row(l, r), p.m - 1);
+        cin[j][r] = Cin[row + (int64_t)col * p.ldc];
+        if constexpr (MODE == NN_RESIDUAL) din[j][r] = Din[row + (int64_t)col * p.ldd];
+      }
+    }
 #pragma unroll
     for (int j = 0; j < RJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = col0 + c_off + 16 * i + MF::row(l, r);
         const int64_t row = row0 + r_off + 16 * j + l % 16;
-        if (col < p.m && row < p.n) {
-          const double prod = (double)acc[i][j][r];
-          const double cin = (double)Cin[row + (int64_t)col * p.ldc];
-          double out;
-          if constexpr (MODE == NN_UPDATE) out = cin - prod;
-          else if constexpr (MODE == NN_ANALYSIS) out = cin + prod;
-          else out = (double)static_cast<const T*>(p.Din)[row + (int64_t)col * p.ldd] - (p.r[row] * cin + prod);
-          Cout[row + (int64_t)col * p.ldo] = (T)out;
-        }
+        const double prod = (double)acc[i][j][r];
+        const double c = (double)cin[j][r];
+        double out;
+        if constexpr (MODE == NN_UPDATE) out = c - prod;
+        else if constexpr (MODE == NN_ANALYSIS) out = c + prod;
+        else out = (double)din[j][r] - (rr[j] * c + prod);
+        if (col < p.m && row < p.n) Cout[row + (int64_t)col * p.ldo] = (T)out;
       }
+  }
 }
 
 constexpr int64_t kTnTargetBlocks = 768;   // ~3 blocks per CU
@@ -401,17 +458,28 @@ enkf_status launch_tn(enkf_dtype dt, int64_t n, int a, int m, const void* A, int
   rpc = ((rpc + kc - 1) / kc) * kc;
   const int64_t used = (n + rpc - 1) / rpc;
   const int tiles_m = (m + TILE - 1) / TILE;
-  const int tiles = ((a + TILE - 1) / TILE) * tiles_m;
-  if (tiles > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "tn product: too many output tiles");
   const size_t es = dt == ENKF_F64 ? 8 : 4;
-  const bool vec = aligned16(A, lda, es) && aligned16(B, ldb, es);
-  dim3 grid((unsigned)used, (unsigned)tiles);
-  if (dt == ENKF_F64)
-    tn_partial_kernel<double><<<grid, NT, 0, s>>>(n, a, m, (const double*)A, lda, (const double*)B, ldb, partial, rpc,
-                                                  tiles_m, vec);
-  else
-    tn_partial_kernel<float><<<grid, NT, 0, s>>>(n, a, m, (const float*)A, lda, (const float*)B, ldb, partial, rpc,
-                                                 tiles_m, vec);
+  const int W = 16 / (int)es;
+  const bool vec = aligned16(A, lda, es) && aligned16(B, ldb, es) && n % W == 0;
+  if (dt == ENKF_F64) {
+    constexpr int WA = tn_wa<double>();
+    const int tiles = ((a + 32 * WA - 1) / (32 * WA)) * tiles_m;
+    if (tiles > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "tn product: too many output tiles");
+    dim3 grid((unsigned)used, (unsigned)tiles);
+    const double* a_ = static_cast<const double*>(A);
+    const double* b_ = static_cast<const double*>(B);
+    if (vec) tn_partial_kernel<double, true, WA><<<grid, 128 * WA, 0, s>>>(n, a, m, a_, lda, b_, ldb, partial, rpc, tiles_m);
+    else tn_partial_kernel<double, false, WA><<<grid, 128 * WA, 0, s>>>(n, a, m, a_, lda, b_, ldb, partial, rpc, tiles_m);
+  } else {
+    constexpr int WA = tn_wa<float>();
+    const int tiles = ((a + 32 * WA - 1) / (32 * WA)) * tiles_m;
+    if (tiles > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "tn product: too many output tiles");
+    dim3 grid((unsigned)used, (unsigned)tiles);
+    const float* a_ = static_cast<const float*>(A);
+    const float* b_ = static_cast<const float*>(B);
+    if (vec) tn_partial_kernel<float, true, WA><<<grid, 128 * WA, 0, s>>>(n, a, m, a_, lda, b_, ldb, partial, rpc, tiles_m);
+    else tn_partial_kernel<float, false, WA><<<grid, 128 * WA, 0, s>>>(n, a, m, a_, lda, b_, ldb, partial, rpc, tiles_m);
+  }
   ENKF_HIP_CHECK(hipGetLastError());
   return launch_partial_sum(a, m, used, partial, G, ldg, s);
 }
@@ -424,20 +492,23 @@ enkf_status launch_partial_sum(int a, int m, int64_t chunks, const double* parti
   return ENKF_SUCCESS;
 }
 
-int nn_bt_ld(int K) { return (K + 15) / 16 * 16; }
+// rows: a multiple of the largest stage depth (32); columns: of the widest tile (128)
+int nn_bt_rows(int K) { return (K + 31) / 32 * 32; }
+int nn_bt_cols(int m) { return (m + 127) / 128 * 128; }
 
-size_t nn_bt_bytes(int K, int m) { return sizeof(double) * (size_t)nn_bt_ld(K) * (size_t)m; }
+size_t nn_bt_bytes(int K, int m) { return sizeof(double) * (size_t)nn_bt_rows(K) * (size_t)nn_bt_cols(m); }
 
 namespace {
 
 template <typename T, int MODE, int TR, int TC>
-enkf_status nn_go(NnArgs p, const T* Bt, int ldbt, bool vec, hipStream_t s) {
+enkf_status nn_go(NnArgs p, const T* Bt, int ldbc, bool vec, hipStream_t s) {
   p.n_row_tiles = (p.n + TR - 1) / TR;
   p.n_col_tiles = (p.m + TC - 1) / TC;
   const int64_t groups = (p.n_row_tiles + 7) / 8;
   const int64_t blocks = groups * 8 * p.n_col_tiles;
   if (blocks > 0x7fffffff) return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
-  nn_kernel<T, MODE, TR, TC><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbt, vec);
+  if (vec) nn_kernel<T, MODE, TR, TC, true><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
+  else nn_kernel<T, MODE, TR, TC, false><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
@@ -445,23 +516,23 @@ enkf_status nn_go(NnArgs p, const T* Bt, int ldbt, bool vec, hipStream_t s) {
 // Tile choice: one column tile of 128 when m <= 128 (64 rows), else
 // 128 rows x 64 (FP64) or 128 (FP32) columns.
 template <typename T, int MODE>
-enkf_status nn_pick(NnArgs p, const T* Bt, int ldbt, bool vec, hipStream_t s) {
-  if (p.m <= 128) return nn_go<T, MODE, 64, 128>(p, Bt, ldbt, vec, s);
-  if constexpr (sizeof(T) == 8) return nn_go<T, MODE, 128, 64>(p, Bt, ldbt, vec, s);
-  else return nn_go<T, MODE, 128, 128>(p, Bt, ldbt, vec, s);
+enkf_status nn_pick(NnArgs p, const T* Bt, int ldbc, bool vec, hipStream_t s) {
+  if (p.m <= 128) return nn_go<T, MODE, 64, 128>(p, Bt, ldbc, vec, s);
+  if constexpr (sizeof(T) == 8) return nn_go<T, MODE, 128, 64>(p, Bt, ldbc, vec, s);
+  else return nn_go<T, MODE, 128, 128>(p, Bt, ldbc, vec, s);
 }
 
 template <typename T>
 enkf_status nn_typed(int mode, NnArgs p, hipStream_t s) {
   T* Bt = static_cast<T*>(p.bws);
-  const int ldbt = nn_bt_ld(p.K);
-  const int64_t total = (int64_t)ldbt * p.m;
-  convert_b_kernel<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(p.K, p.m, p.Bm, p.ldb, p.scale, Bt, ldbt);
+  const int rows = nn_bt_rows(p.K), ldbc = nn_bt_cols(p.m);
+  const int64_t total = (int64_t)rows * ldbc;
+  convert_b_kernel<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(p.K, p.m, p.Bm, p.ldb, p.scale, Bt, rows, ldbc);
   ENKF_HIP_CHECK(hipGetLastError());
-  const bool vec = aligned16(p.A, p.lda, sizeof(T));
-  if (mode == NN_UPDATE) return nn_pick<T, NN_UPDATE>(p, Bt, ldbt, vec, s);
-  if (mode == NN_ANALYSIS) return nn_pick<T, NN_ANALYSIS>(p, Bt, ldbt, vec, s);
-  return nn_pick<T, NN_RESIDUAL>(p, Bt, ldbt, vec, s);
+  const bool vec = aligned16(p.A, p.lda, sizeof(T)) && p.n % (int64_t)(16 / sizeof(T)) == 0;
+  if (mode == NN_UPDATE) return nn_pick<T, NN_UPDATE>(p, Bt, ldbc, vec, s);
+  if (mode == NN_ANALYSIS) return nn_pick<T, NN_ANALYSIS>(p, Bt, ldbc, vec, s);
+  return nn_pick<T, NN_RESIDUAL>(p, Bt, ldbc, vec, s);
 }
 
 }  // namespace
