@@ -7,10 +7,11 @@
 //           takes the six cross products down to 2^-24 (six passes)
 //   F16X2   x -> hi + lo/2^11, hi = f16(x), lo = f16((x - hi) 2^11); the
 //           cross terms go to a second accumulator scaled by 2^-11 at the end
-// Same two products as gemm_mfma.hip:
+// Same two products as gemm_mfma.hip, with the same pipeline (branch-free
+// register prefetch of the next stage kept ahead of the matrix-core work):
 //   tn: P = A^T B over n rows, split-K partials (FP64), fixed-order sum;
-//   nn: X <- X - A Bm (UPDATE) and XA <- XB + (XB - xbar 1^T)(s Bm) (ANALYSIS).
-// FP32 accumulators are emptied into FP64 every stage of rows (tn).
+//   nn: X <- X - A Bm (UPDATE) and XA <- XB + (XB - xbar 1^T)(s Bm) (ANALYSIS);
+//       the right factor is split into its narrow parts once per call.
 #include "enkf_internal.h"
 #include "gemm_lowp.h"
 #include "gemm_mfma.h"
@@ -90,105 +91,75 @@ __device__ __forceinline__ V ld8(const void* p) {
   return *reinterpret_cast<const V*>(p);
 }
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Branch-free staged loads (as in gemm_mfma.hip): an index outside the valid
+// range reads a valid element; values that matter are zeroed when staged.
+template <bool VEC>
+__device__ __forceinline__ f4v load4(const float* __restrict__ col, int64_t row, int64_t rlim) {
+  f4v v;
+  if constexpr (VEC) {
+    v = *reinterpret_cast<const f4v*>(col + (row < rlim ? row : 0));
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = col[row + e < rlim ? row + e : 0];
+  }
+  return v;
+}
+
 // ---------------------------------------------------------------- tn
-// Stage layout: hi/lo[col][k], col in [0, 2*TILE): A columns then B columns.
-template <int MATH>
-__global__ __launch_bounds__(NT) void tn_lowp_kernel(int64_t n, int a, int m, const float* __restrict__ A, int64_t lda,
-                                                     const float* __restrict__ B, int64_t ldb,
-                                                     double* __restrict__ partial, int64_t rows_per_chunk, int tiles_m,
-                                                     bool vec) {
+// Stage layout: S[q][col][k] per part q, col in [0, TA + TILE): A columns
+// then B columns; k contiguous (LDK), so an MFMA operand is one 16-byte read.
+// 4 waves, 2 (m) x 2 (a); wave tile 64 x 32 (4 x 2 MFMA tiles); block tile
+// 128 (m) x 64 (a). FP32 accumulators are emptied into FP64 every kFlush
+// stages (one-pass forms: their own rounding dominates, so less often).
+constexpr int TA = 64;
+
+template <int MATH, bool VEC>
+__global__ __launch_bounds__(NT, 2) void tn_lowp_kernel(int64_t n, int a, int m, const float* __restrict__ A,
+                                                        int64_t lda, const float* __restrict__ B, int64_t ldb,
+                                                        double* __restrict__ partial, int64_t rows_per_chunk,
+                                                        int tiles_m) {
   typedef Lp<MATH> P;
   typedef typename P::e_t E;
   typedef typename P::v_t VT;
-  typedef float f4v __attribute__((ext_vector_type(4)));
-  constexpr int COLS = 2 * TILE;
+  constexpr int COLS = TA + TILE;
   constexpr int PER_COL = KC / 4;
   constexpr int COLS_PER_PASS = NT / PER_COL;
   constexpr int PASSES = COLS / COLS_PER_PASS;
+  constexpr int kFlush = P::PARTS == 1 ? 8 : 2;
   __shared__ __attribute__((aligned(16))) E S[P::PARTS][COLS * LDK];
 
   const int ta = blockIdx.y / tiles_m, tm = blockIdx.y % tiles_m;
-  const int a0 = ta * TILE, m0 = tm * TILE;
+  const int a0 = ta * TA, m0 = tm * TILE;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
   const int64_t r1 = min(n, r0 + rows_per_chunk);
   const int t = threadIdx.x, l = t % kWave, w = t / kWave;
-  const int m_off = (w / 2) * 64, a_off = (w % 2) * 64;
+  const int m_off = (w / 2) * 64, a_off = (w % 2) * 32;
   const int lc = t / PER_COL, lk = (t % PER_COL) * 4;
   const float* cp[PASSES];
 #pragma unroll
   for (int p = 0; p < PASSES; ++p) {
     const int c = p * COLS_PER_PASS + lc;
-    if (c < TILE) cp[p] = (a0 + c < a) ? A + (int64_t)(a0 + c) * lda : nullptr;
-    else cp[p] = (m0 + c - TILE < m) ? B + (int64_t)(m0 + c - TILE) * ldb : nullptr;
+    if (c < TA) cp[p] = A + (int64_t)min(a0 + c, a - 1) * lda;
+    else cp[p] = B + (int64_t)min(m0 + c - TA, m - 1) * ldb;
   }
-  mf_f4 acc[4][4], acc2[P::has_scaled ? 4 : 1][P::has_scaled ? 4 : 1];
-  double wide[4][4][4];
+  mf_f4 acc[4][2], acc2[P::has_scaled ? 4 : 1][P::has_scaled ? 2 : 1];
+  double wide[4][2][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 2; ++j) {
       acc[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (P::has_scaled) acc2[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int r = 0; r < 4; ++r) wide[i][j][r] = 0.0;
     }
-  if constexpr (P::has_scaled) {
+  auto flush = [&]() {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc2[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
-  }
-  f4v reg[PASSES];
-  for (int64_t rs = r0; rs < r1; rs += KC) {
-#pragma unroll
-    for (int p = 0; p < PASSES; ++p) {
-      f4v v = {0.f, 0.f, 0.f, 0.f};
-      if (cp[p]) {
-        const int64_t row = rs + lk;
-        if (vec && row + 4 <= r1) v = *reinterpret_cast<const f4v*>(cp[p] + row);
-        else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (row + e < r1) ? cp[p][row + e] : 0.f;
-        }
-      }
-      reg[p] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < PASSES; ++p) {
-      const int o = (p * COLS_PER_PASS + lc) * LDK + lk;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        E parts[P::PARTS];
-        P::conv(reg[p][e], parts);
-#pragma unroll
-        for (int q = 0; q < P::PARTS; ++q) S[q][o + e] = parts[q];
-      }
-    }
-    __syncthreads();
-    VT bo[P::PARTS][4], ao[P::PARTS][4];
-#pragma unroll
-    for (int q = 0; q < P::PARTS; ++q) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) bo[q][i] = ld8<VT>(&S[q][(TILE + m_off + 16 * i + l % 16) * LDK + 8 * (l / 16)]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) ao[q][j] = ld8<VT>(&S[q][(a_off + 16 * j + l % 16) * LDK + 8 * (l / 16)]);
-    }
-#pragma unroll
-    for (int pr = 0; pr < P::NPROD; ++pr) {
-      const int pa = kPA[pr], pb = kPB[pr];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (P::has_scaled && pr > 0) acc2[i][j] = P::mma(bo[pa][i], ao[pb][j], acc2[i][j]);
-          else acc[i][j] = P::mma(bo[pa][i], ao[pb][j], acc[i][j]);
-        }
-    }
-    // empty the FP32 accumulators into FP64 after every stage
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 2; ++j) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           double v = (double)acc[i][j][r];
@@ -198,12 +169,69 @@ __global__ __launch_bounds__(NT) void tn_lowp_kernel(int64_t n, int a, int m, co
         acc[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
         if constexpr (P::has_scaled) acc2[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
       }
+  };
+  f4v reg[PASSES];
+  auto fetch = [&](int64_t rs) {
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) reg[p] = load4<VEC>(cp[p], rs + lk, r1);
+  };
+  auto stash = [&](int64_t rs) {
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) {
+      const int o = (p * COLS_PER_PASS + lc) * LDK + lk;
+      E parts[4][P::PARTS];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) P::conv(rs + lk + e < r1 ? reg[p][e] : 0.f, parts[e]);
+#pragma unroll
+      for (int q = 0; q < P::PARTS; ++q) {
+        typedef E e4 __attribute__((ext_vector_type(4)));
+        e4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = parts[e][q];
+        *reinterpret_cast<e4*>(&S[q][o]) = v;
+      }
+    }
+  };
+  if (r0 < r1) {
+    fetch(r0);
+    stash(r0);
   }
+  __syncthreads();
+  int stage = 0;
+  for (int64_t rs = r0; rs < r1; rs += KC) {
+    fetch(rs + KC);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int pr = 0; pr < P::NPROD; ++pr) {
+      const int pa = kPA[pr], pb = kPB[pr];
+      VT bo[4], ao[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bo[i] = ld8<VT>(&S[pa][(TA + m_off + 16 * i + l % 16) * LDK + 8 * (l / 16)]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) ao[j] = ld8<VT>(&S[pb][(a_off + 16 * j + l % 16) * LDK + 8 * (l / 16)]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (P::has_scaled && pr > 0) acc2[i][j] = P::mma(bo[i], ao[j], acc2[i][j]);
+          else acc[i][j] = P::mma(bo[i], ao[j], acc[i][j]);
+        }
+    }
+    if (++stage == kFlush) {
+      flush();
+      stage = 0;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    stash(rs + KC);
+    __syncthreads();
+  }
+  flush();
   double* Pp = partial + (int64_t)blockIdx.x * a * m;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int mi = m0 + m_off + 16 * i + 4 * (l / 16) + r;
@@ -213,142 +241,244 @@ __global__ __launch_bounds__(NT) void tn_lowp_kernel(int64_t n, int a, int m, co
 }
 
 // ---------------------------------------------------------------- nn
-// A-side stage: hi/lo[row][k] (8 k per 16-byte group); B-side: [col][k].
-template <int MATH, int MODE>
-__global__ __launch_bounds__(NT) void nn_lowp_kernel(NnArgs p) {
+// The right factor scale * Bm is split into parts once per call:
+// Bp[q][col * ldk + k], ldk = nn_bt_rows(K) (zero past K), columns padded to
+// nn_bt_cols(m) (zero past m).
+template <int MATH>
+__global__ __launch_bounds__(256) void split_b_kernel(int K, int m, const double* __restrict__ Bm, int64_t ldb,
+                                                      double scale, typename Lp<MATH>::e_t* __restrict__ Bp, int ldk,
+                                                      int cols) {
+  typedef Lp<MATH> P;
+  typedef typename P::e_t E;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)ldk * cols;
+  if (e >= total) return;
+  const int k = (int)(e % ldk), j = (int)(e / ldk);
+  const float x = (k < K && j < m) ? (float)(scale * Bm[k + (int64_t)j * ldb]) : 0.f;
+  E parts[P::PARTS];
+  P::conv(x, parts);
+#pragma unroll
+  for (int q = 0; q < P::PARTS; ++q) Bp[q * total + e] = parts[q];
+}
+
+// Stage layout: As[q][row][k], Bs[q][col][k] (k contiguous, LDK). A items:
+// 4 rows x 4 k (four 16-byte column loads, four 8-byte LDS writes per part);
+// B items: 8 k of one column (one 16-byte load and write per part).
+// 4 waves, 2 x 2: wave (w/2, w%2) owns TC/2 columns x TR/2 rows.
+template <int MATH, int MODE, int TR, int TC, bool VEC>
+__global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename Lp<MATH>::e_t* __restrict__ Bp,
+                                                        int ldk, int64_t bp_stride) {
   typedef Lp<MATH> P;
   typedef typename P::e_t E;
   typedef typename P::v_t VT;
-  __shared__ __attribute__((aligned(16))) E As[P::PARTS][TILE * LDK];
-  __shared__ __attribute__((aligned(16))) E Bs[P::PARTS][TILE * LDK];
-  __shared__ double mean[TILE];
+  constexpr int CI = TC / 32, RJ = TR / 32;
+  constexpr int KE = TR * KC / (4 * NT);           // k per A item (4 rows x KE k)
+  static_assert(KE == 2 || KE == 4, "A item shape");
+  constexpr int A_ITEMS = (TR / 4) * (KC / KE);
+  constexpr int A_PASSES = A_ITEMS / NT;
+  constexpr int B_ITEMS = TC * (KC / 8);
+  constexpr int B_PASSES = B_ITEMS / NT;
+  static_assert(A_PASSES >= 1 && B_PASSES >= 1, "tile too small for the block");
+  __shared__ __attribute__((aligned(16))) E As[P::PARTS][TR * LDK];
+  __shared__ __attribute__((aligned(16))) E Bs[P::PARTS][TC * LDK];
+  __shared__ double mean[TR];
   int64_t rt;
   int ct;
   xcd_tile_map(blockIdx.x, p.n_row_tiles, p.n_col_tiles, &rt, &ct);
   if (rt >= p.n_row_tiles) return;
-  const int64_t row0 = rt * TILE;
-  const int col0 = ct * TILE;
+  const int64_t row0 = rt * TR;
+  const int col0 = ct * TC;
   const float* __restrict__ A = static_cast<const float*>(p.A);
   const int t = threadIdx.x, l = t % kWave, w = t / kWave;
-  const int c_off = (w / 2) * 64, r_off = (w % 2) * 64;
+  const int c_off = (w / 2) * (TC / 2), r_off = (w % 2) * (TR / 2);
+  const int64_t rlim = p.n;
   if constexpr (MODE == NN_ANALYSIS) {
-    __shared__ double part[2][TILE];
-    const int rr = t % TILE, q = t / TILE;
-    const int64_t row = row0 + rr;
+    constexpr int Q = NT / TR;
+    constexpr int U = 8;
+    __shared__ double part[Q][TR];
+    const int rr = t % TR, q = t / TR;
+    const float* __restrict__ ar = A + min(row0 + rr, rlim - 1);
     double s = 0.0;
-    if (row < p.n)
-      for (int j = q; j < p.K; j += 2) s += (double)A[row + (int64_t)j * p.lda];
+    int j = q;
+    for (; j + (U - 1) * Q < p.K; j += U * Q) {
+      float x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = ar[(int64_t)(j + u * Q) * p.lda];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += (double)x[u];
+    }
+    for (; j < p.K; j += Q) s += (double)ar[(int64_t)j * p.lda];
     part[q][rr] = s;
     __syncthreads();
-    if (t < TILE) mean[t] = (part[0][t] + part[1][t]) / (double)p.K;
+    if (t < TR) {
+      double tot = 0.0;
+#pragma unroll
+      for (int z = 0; z < Q; ++z) tot += part[z][t];
+      mean[t] = tot / (double)p.K;
+    }
     __syncthreads();
   }
-  mf_f4 acc[4][4], acc2[P::has_scaled ? 4 : 1][P::has_scaled ? 4 : 1];
+  mf_f4 acc[CI][RJ], acc2[P::has_scaled ? CI : 1][P::has_scaled ? RJ : 1];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < CI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
-  if constexpr (P::has_scaled) {
+    for (int j = 0; j < RJ; ++j) {
+      acc[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (P::has_scaled) acc2[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  f4v areg[A_PASSES][KE];
+  VT breg[B_PASSES][P::PARTS];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int q = 0; q < A_PASSES; ++q) {
+      const int it = q * NT + t;
+      const int rq = (it % (TR / 4)) * 4, kq = (it / (TR / 4)) * KE;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc2[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
-  }
+      for (int e = 0; e < KE; ++e) {
+        const int k = min(k0 + kq + e, p.K - 1);
+        areg[q][e] = load4<VEC>(A + (int64_t)k * p.lda, row0 + rq, rlim);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < B_PASSES; ++q) {
+      const int it = q * NT + t;
+      const int cc = it % TC, kg = (it / TC) * 8;
+      const int k = min(k0 + kg, ldk - 8);
+#pragma unroll
+      for (int z = 0; z < P::PARTS; ++z)
+        breg[q][z] = ld8<VT>(Bp + z * bp_stride + (int64_t)(col0 + cc) * ldk + k);
+    }
+  };
+  auto stash = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < A_PASSES; ++q) {
+      const int it = q * NT + t;
+      const int rq = (it % (TR / 4)) * 4, kq = (it / (TR / 4)) * KE;
+      // element (row rq + x, k kq + e) = areg[q][e][x]
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        E parts[KE][P::PARTS];
+#pragma unroll
+        for (int e = 0; e < KE; ++e) {
+          float v = areg[q][e][x];
+          if constexpr (MODE == NN_ANALYSIS) v = (float)((double)v - mean[rq + x]);
+          P::conv(k0 + kq + e < p.K ? v : 0.f, parts[e]);
+        }
+#pragma unroll
+        for (int z = 0; z < P::PARTS; ++z) {
+          typedef E ek __attribute__((ext_vector_type(KE)));
+          ek vk;
+#pragma unroll
+          for (int e = 0; e < KE; ++e) vk[e] = parts[e][z];
+          *reinterpret_cast<ek*>(&As[z][(rq + x) * LDK + kq]) = vk;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < B_PASSES; ++q) {
+      const int it = q * NT + t;
+      const int cc = it % TC, kg = (it / TC) * 8;
+#pragma unroll
+      for (int z = 0; z < P::PARTS; ++z) *reinterpret_cast<VT*>(&Bs[z][cc * LDK + kg]) = breg[q][z];
+    }
+  };
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
   for (int k0 = 0; k0 < p.K; k0 += KC) {
-    // A-side items: (row, 8-k group): TILE rows x KC/8 groups = 512 items
-    float av[2][8];
-    double bv[2][8];
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int item = it * NT + t;
-      const int rr = item % TILE, kg = item / TILE;
-      const int64_t row = row0 + rr;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = k0 + 8 * kg + e;
-        float v = 0.f;
-        if (row < p.n && k < p.K) {
-          v = A[row + (int64_t)k * p.lda];
-          if constexpr (MODE == NN_ANALYSIS) v = (float)((double)v - mean[rr]);
-        }
-        av[it][e] = v;
-      }
-      // B-side items: (col, 8-k group): TILE cols x KC/8 groups
-      const int cc = item % TILE;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = k0 + 8 * kg + e;
-        bv[it][e] = (k < p.K && col0 + cc < p.m) ? p.scale * p.Bm[k + (int64_t)(col0 + cc) * p.ldb] : 0.0;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int item = it * NT + t;
-      const int rr = item % TILE, kg = item / TILE;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        E pa[P::PARTS], pb[P::PARTS];
-        P::conv(av[it][e], pa);
-        P::conv((float)bv[it][e], pb);
-#pragma unroll
-        for (int q = 0; q < P::PARTS; ++q) {
-          As[q][rr * LDK + 8 * kg + e] = pa[q];
-          Bs[q][rr * LDK + 8 * kg + e] = pb[q];
-        }
-      }
-    }
-    __syncthreads();
-    VT co[P::PARTS][4], ro[P::PARTS][4];
-#pragma unroll
-    for (int q = 0; q < P::PARTS; ++q) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) co[q][i] = ld8<VT>(&Bs[q][(c_off + 16 * i + l % 16) * LDK + 8 * (l / 16)]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) ro[q][j] = ld8<VT>(&As[q][(r_off + 16 * j + l % 16) * LDK + 8 * (l / 16)]);
-    }
+    fetch(k0 + KC);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int pr = 0; pr < P::NPROD; ++pr) {
       const int pa = kPA[pr], pb = kPB[pr];
+      VT co[CI], ro[RJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < CI; ++i) co[i] = ld8<VT>(&Bs[pa][(c_off + 16 * i + l % 16) * LDK + 8 * (l / 16)]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (P::has_scaled && pr > 0) acc2[i][j] = P::mma(co[pa][i], ro[pb][j], acc2[i][j]);
-          else acc[i][j] = P::mma(co[pa][i], ro[pb][j], acc[i][j]);
+      for (int j = 0; j < RJ; ++j) ro[j] = ld8<VT>(&As[pb][(r_off + 16 * j + l % 16) * LDK + 8 * (l / 16)]);
+#pragma unroll
+      for (int i = 0; i < CI; ++i)
+#pragma unroll
+        for (int j = 0; j < RJ; ++j) {
+          if (P::has_scaled && pr > 0) acc2[i][j] = P::mma(co[i], ro[j], acc2[i][j]);
+          else acc[i][j] = P::mma(co[i], ro[j], acc[i][j]);
         }
     }
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    stash(k0 + KC);
+    __syncthreads();
   }
+  // epilogue: inputs loaded first (clamped, branch-free), stores predicated
   float* __restrict__ Cout = static_cast<float*>(p.Cout);
   const float* __restrict__ Cin = static_cast<const float*>(p.Cin);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < CI; ++i) {
+    float cin[RJ][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < RJ; ++j) {
+      const int64_t row = min(row0 + r_off + 16 * j + l % 16, rlim - 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = min(col0 + c_off + 16 * i + 4 * (l / 16) + r, p.m - 1);
+        cin[j][r] = Cin[row + (int64_t)col * p.ldc];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = col0 + c_off + 16 * i + 4 * (l / 16) + r;
         const int64_t row = row0 + r_off + 16 * j + l % 16;
-        if (col < p.m && row < p.n) {
-          double prod = (double)acc[i][j][r];
-          if constexpr (P::has_scaled) prod += (double)acc2[i][j][r] * (double)kLoScale;
-          const double cin = (double)Cin[row + (int64_t)col * p.ldc];
-          const double out = (MODE == NN_UPDATE) ? cin - prod : cin + prod;
-          Cout[row + (int64_t)col * p.ldo] = (float)out;
-        }
+        double prod = (double)acc[i][j][r];
+        if constexpr (P::has_scaled) prod += (double)acc2[i][j][r] * (double)kLoScale;
+        const double c = (double)cin[j][r];
+        const double out = (MODE == NN_UPDATE) ? c - prod : c + prod;
+        if (col < p.m && row < p.n) Cout[row + (int64_t)col * p.ldo] = (float)out;
       }
+  }
 }
 
 template <int MATH>
 void tn_launch(dim3 grid, hipStream_t s, int64_t n, int a, int m, const float* A, int64_t lda, const float* B,
                int64_t ldb, double* partial, int64_t rpc, int tiles_m, bool vec) {
-  tn_lowp_kernel<MATH><<<grid, NT, 0, s>>>(n, a, m, A, lda, B, ldb, partial, rpc, tiles_m, vec);
+  if (vec) tn_lowp_kernel<MATH, true><<<grid, NT, 0, s>>>(n, a, m, A, lda, B, ldb, partial, rpc, tiles_m);
+  else tn_lowp_kernel<MATH, false><<<grid, NT, 0, s>>>(n, a, m, A, lda, B, ldb, partial, rpc, tiles_m);
+}
+
+template <int MATH, int MODE, int TR, int TC>
+void nn_go(NnArgs p, const typename Lp<MATH>::e_t* Bp, int ldk, int64_t stride, bool vec, hipStream_t s) {
+  p.n_row_tiles = (p.n + TR - 1) / TR;
+  p.n_col_tiles = (p.m + TC - 1) / TC;
+  const int64_t groups = (p.n_row_tiles + 7) / 8;
+  const unsigned g = (unsigned)(groups * 8 * p.n_col_tiles);
+  if (vec) nn_lowp_kernel<MATH, MODE, TR, TC, true><<<g, NT, 0, s>>>(p, Bp, ldk, stride);
+  else nn_lowp_kernel<MATH, MODE, TR, TC, false><<<g, NT, 0, s>>>(p, Bp, ldk, stride);
 }
 
 template <int MATH>
-void nn_launch(unsigned g, hipStream_t s, int mode, const NnArgs& p) {
-  if (mode == NN_ANALYSIS) nn_lowp_kernel<MATH, NN_ANALYSIS><<<g, NT, 0, s>>>(p);
-  else nn_lowp_kernel<MATH, NN_UPDATE><<<g, NT, 0, s>>>(p);
+enkf_status nn_launch(hipStream_t s, int mode, NnArgs p) {
+  typedef typename Lp<MATH>::e_t E;
+  E* Bp = static_cast<E*>(p.bws);
+  const int ldk = nn_bt_rows(p.K), cols = nn_bt_cols(p.m);
+  const int64_t stride = (int64_t)ldk * cols;
+  split_b_kernel<MATH><<<(unsigned)((stride + 255) / 256), 256, 0, s>>>(p.K, p.m, p.Bm, p.ldb, p.scale, Bp, ldk, cols);
+  ENKF_HIP_CHECK(hipGetLastError());
+  const int64_t rows = (p.n + 63) / 64;
+  if ((p.m <= 128 ? rows : (p.n + 127) / 128) * 8 * ((p.m + 127) / 128) > 0x7fffffff)
+    return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
+  const bool vec = ((uintptr_t)p.A % 16) == 0 && (p.lda % 4) == 0 && (p.n % 4) == 0;
+  if (p.m <= 128) {
+    if (mode == NN_ANALYSIS) nn_go<MATH, NN_ANALYSIS, 64, 128>(p, Bp, ldk, stride, vec, s);
+    else nn_go<MATH, NN_UPDATE, 64, 128>(p, Bp, ldk, stride, vec, s);
+  } else {
+    if (mode == NN_ANALYSIS) nn_go<MATH, NN_ANALYSIS, 128, 128>(p, Bp, ldk, stride, vec, s);
+    else nn_go<MATH, NN_UPDATE, 128, 128>(p, Bp, ldk, stride, vec, s);
+  }
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
 }
 
 }  // namespace
@@ -361,9 +491,10 @@ enkf_status launch_tn_lowp(enkf_math math, int64_t n, int a, int m, const float*
   rpc = ((rpc + KC - 1) / KC) * KC;
   const int64_t used = (n + rpc - 1) / rpc;
   const int tiles_m = (m + TILE - 1) / TILE;
-  const int tiles = ((a + TILE - 1) / TILE) * tiles_m;
+  const int tiles = ((a + TA - 1) / TA) * tiles_m;
   if (tiles > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "tn product: too many output tiles");
-  const bool vec = ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0 && (lda % 4) == 0 && (ldb % 4) == 0;
+  const bool vec = ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0 && (lda % 4) == 0 && (ldb % 4) == 0 &&
+                   (n % 4) == 0;
   dim3 grid((unsigned)used, (unsigned)tiles);
   switch (math) {
     case ENKF_MATH_BF16: tn_launch<ENKF_MATH_BF16>(grid, s, n, a, m, A, lda, B, ldb, partial, rpc, tiles_m, vec); break;
@@ -381,21 +512,14 @@ enkf_status launch_tn_lowp(enkf_math math, int64_t n, int a, int m, const float*
 enkf_status launch_nn_lowp(enkf_math math, int mode, NnArgs p, hipStream_t s) {
   if (p.n <= 0 || p.m <= 0) return ENKF_SUCCESS;
   if (mode == NN_RESIDUAL) return fail(ENKF_ERR_NOT_SUPPORTED, "the residual is formed in FP64");
-  p.n_row_tiles = (p.n + TILE - 1) / TILE;
-  p.n_col_tiles = (p.m + TILE - 1) / TILE;
-  const int64_t groups = (p.n_row_tiles + 7) / 8;
-  const int64_t blocks = groups * 8 * p.n_col_tiles;
-  if (blocks > 0x7fffffff) return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
-  const unsigned g = (unsigned)blocks;
+  if (!p.bws) return fail(ENKF_ERR_INVALID_ARG, "nn product: no workspace for the split right factor");
   switch (math) {
-    case ENKF_MATH_BF16: nn_launch<ENKF_MATH_BF16>(g, s, mode, p); break;
-    case ENKF_MATH_F16: nn_launch<ENKF_MATH_F16>(g, s, mode, p); break;
-    case ENKF_MATH_BF16X3: nn_launch<ENKF_MATH_BF16X3>(g, s, mode, p); break;
-    case ENKF_MATH_F16X2: nn_launch<ENKF_MATH_F16X2>(g, s, mode, p); break;
+    case ENKF_MATH_BF16: return nn_launch<ENKF_MATH_BF16>(s, mode, p);
+    case ENKF_MATH_F16: return nn_launch<ENKF_MATH_F16>(s, mode, p);
+    case ENKF_MATH_BF16X3: return nn_launch<ENKF_MATH_BF16X3>(s, mode, p);
+    case ENKF_MATH_F16X2: return nn_launch<ENKF_MATH_F16X2>(s, mode, p);
     default: return fail(ENKF_ERR_INVALID_ARG, "nn product: not a narrow math type");
   }
-  ENKF_HIP_CHECK(hipGetLastError());
-  return ENKF_SUCCESS;
 }
 
 }  // namespace enkf

@@ -30,7 +30,10 @@ enkf_status launch_tn(enkf_dtype dt, int64_t n, int a, int m, const void* A, int
                       double* G, int64_t ldg, double* partial, hipStream_t s);
 
 enkf_status launch_nn(enkf_dtype dt, int mode, NnArgs p, hipStream_t s);
-// Workspace bytes of the converted right factor of an nn product.
+// Converted right factor of an nn product: padded rows (multiple of 32),
+// padded columns (multiple of 128), workspace bytes.
+int nn_bt_rows(int K);
+int nn_bt_cols(int m);
 size_t nn_bt_bytes(int K, int m);
 // G (a x m, ldg) = sum over `chunks` partials of a x m (fixed order).
 enkf_status launch_partial_sum(int a, int m, int64_t chunks, const double* partial, double* G, int64_t ldg,

@@ -1,9 +1,9 @@
 // Small kernels of the blocked solve (gfx950):
 //  - Step 1 as a row scaling, Y = R^{-1} X (eq. SM-step-1);
 //  - the FP64 factorisation of one panel: with P = V_K^T [U_K, X] (b rows),
-//    M = I + V_K^T U_K (symmetrised) is factored M = L D L^T in LDS; the
-//    pivots D are the gamma_k of the panel's b levels (Section 3.3); the
-//    kernel leaves M^{-1} = L^{-T} D^{-1} L^{-1} for the panel update
+//    M = I + V_K^T U_K (symmetrised) is inverted by symmetric sweeps whose
+//    pivots are those of M = L D L^T, the gamma_k of the panel's b levels
+//    (Section 3.3); the kernel leaves M^{-1} for the panel update
 //    X <- X - U_K M^{-1} V_K^T X (eq. SWM with a rank-b term);
 //  - Q = M^{-1} P_X, a b x m product in FP64.
 #include "enkf_internal.h"
@@ -12,7 +12,6 @@
 namespace enkf {
 namespace {
 
-__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
 
 template <typename T>
 __global__ __launch_bounds__(256) void scale_rows_kernel(int64_t n, int m, const T* __restrict__ X, int64_t ldx,
@@ -26,59 +25,72 @@ __global__ __launch_bounds__(256) void scale_rows_kernel(int64_t n, int m, const
   for (int j = c; j < m; j += gridDim.y) Y[i + (int64_t)j * ldy] = (T)((double)X[i + (int64_t)j * ldx] / rv);
 }
 
-// One block. Dynamic LDS: two packed lower triangles of b(b+1)/2 doubles.
+// One block of 256 threads as a 16 x 16 grid; thread (ti, tj) keeps the
+// elements (i, j) = (ti + 16 r, tj + 16 c), r, c < 8, of the symmetrised
+// M = I + (P_K + P_K^T)/2 in registers. M is inverted in place by b
+// symmetric sweeps (Gauss-Jordan elimination in the natural order, without
+// pivoting, which M being SPD allows): sweep k divides by the current
+// diagonal element k, which is the k-th pivot of M = L D L^T, i.e. the
+// gamma of level k0 + k. After the b sweeps the registers hold -M^{-1}.
+// Only column k is shared per sweep (through LDS, double-buffered: one
+// barrier per sweep).
 __global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* __restrict__ P, int64_t ldp,
                                                            double* __restrict__ gamma_out, double* __restrict__ Minv,
                                                            unsigned* status) {
-  extern __shared__ double sm[];
-  double* Lm = sm;                       // M, then L (strict lower) and D (diagonal)
-  double* Tm = sm + b * (b + 1) / 2;     // L^{-1} (strict lower; unit diagonal implied)
-  const int t = threadIdx.x;
-  for (int i = 0; i < b; ++i)
-    for (int j = t; j <= i; j += 256)
-      Lm[tri(i, j)] = (i == j ? 1.0 : 0.0) + 0.5 * (P[i + (int64_t)j * ldp] + P[j + (int64_t)i * ldp]);
+  __shared__ double col[2][kMaxPanel];
+  const int t = threadIdx.x, ti = t % 16, tj = t / 16;
+  double a[8][8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int i = ti + 16 * r, j = tj + 16 * c;
+      const int ic = min(i, b - 1), jc = min(j, b - 1);
+      const double x = P[ic + (int64_t)jc * ldp], y = P[jc + (int64_t)ic * ldp];
+      a[r][c] = (i < b && j < b) ? (i == j ? 1.0 : 0.0) + 0.5 * (x + y) : 0.0;
+    }
+  if (tj == 0)
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      if (ti + 16 * r < b) col[0][ti + 16 * r] = a[r][0];
   __syncthreads();
-  // right-looking LDL^T
-  const int ti = t % 16, tk = t / 16;
-  for (int j = 0; j < b; ++j) {
-    const double d = Lm[tri(j, j)];
+  for (int k = 0; k < b; ++k) {
+    const double* __restrict__ ck = col[k & 1];
+    double* __restrict__ cn = col[(k + 1) & 1];
+    const double d = ck[k];
     if (t == 0) {
-      gamma_out[j] = d;
+      gamma_out[k] = d;
       if (!(d > 0.0) || !__builtin_isfinite(d)) atomicOr(status, kStatusNotSpd);
     }
-    const double inv_d = 1.0 / d;
-    for (int i = j + 1 + ti; i < b; i += 16) {
-      const double aij = Lm[tri(i, j)];
-      for (int k = j + 1 + tk; k <= i; k += 16) Lm[tri(i, k)] -= aij * Lm[tri(k, j)] * inv_d;
-    }
+    const double inv = 1.0 / d;
+    double ci[8], cj[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) ci[r] = ck[min(ti + 16 * r, b - 1)];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) cj[c] = ck[min(tj + 16 * c, b - 1)];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int i = ti + 16 * r, j = tj + 16 * c;
+        // by symmetry, element (k, j) of the current matrix is ck[j]
+        const double upd = a[r][c] - ci[r] * cj[c] * inv;
+        double v = upd;
+        if (i == k) v = cj[c] * inv;
+        if (j == k) v = ci[r] * inv;
+        if (i == k && j == k) v = -inv;
+        a[r][c] = v;
+        if (j == k + 1 && i < b) cn[i] = v;
+      }
     __syncthreads();
-    for (int i = j + 1 + t; i < b; i += 256) Lm[tri(i, j)] *= inv_d;
-    __syncthreads();
   }
-  // T = L^{-1}, column j by forward substitution (one thread per column:
-  // columns are independent, so no barrier inside)
-  for (int j = t; j < b; j += 256) {
-    for (int i = j + 1; i < b; ++i) {
-      double s = Lm[tri(i, j)];
-      for (int k = j + 1; k < i; ++k) s += Lm[tri(i, k)] * Tm[tri(k, j)];
-      Tm[tri(i, j)] = -s;
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int i = ti + 16 * r, j = tj + 16 * c;
+      if (i < b && j < b) Minv[i + (int64_t)j * b] = -a[r][c];
     }
-  }
-  __syncthreads();
-  // M^{-1} = T^T D^{-1} T (the reciprocal pivots overwrite D)
-  for (int k = t; k < b; k += 256) Lm[tri(k, k)] = 1.0 / Lm[tri(k, k)];
-  __syncthreads();
-  for (int e = t; e < b * b; e += 256) {
-    const int i = e % b, j = e / b;
-    const int k0 = i > j ? i : j;
-    double s = 0.0;
-    for (int k = k0; k < b; ++k) {
-      const double tki = (k == i) ? 1.0 : Tm[tri(k, i)];
-      const double tkj = (k == j) ? 1.0 : Tm[tri(k, j)];
-      s += tki * tkj * Lm[tri(k, k)];
-    }
-    Minv[i + (int64_t)j * b] = s;
-  }
 }
 
 __global__ __launch_bounds__(256) void small_gemm_kernel(int b, int m, const double* __restrict__ Minv,
@@ -214,14 +226,7 @@ enkf_status launch_scale_rows(enkf_dtype dt, int64_t n, int m, const void* X, in
 enkf_status launch_panel_factor(int b, const double* P, int64_t ldp, double* gamma_out, double* Minv, unsigned* status,
                                 hipStream_t s) {
   if (b < 1 || b > kMaxPanel) return fail(ENKF_ERR_NOT_SUPPORTED, "panel width outside [1, 128]");
-  const size_t lds = sizeof(double) * (size_t)b * (b + 1);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)panel_factor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double) * kMaxPanel * (kMaxPanel + 1)));
-    attr_set = true;
-  }
-  panel_factor_kernel<<<1, 256, lds, s>>>(b, P, ldp, gamma_out, Minv, status);
+  panel_factor_kernel<<<1, 256, 0, s>>>(b, P, ldp, gamma_out, Minv, status);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
