@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}
 METRIC = "analysis solves/sec + HBM GB/s or MFMA TFLOP/s, mixed vs plain FP64 at stated residual"
 CLASSES = ("factor_sweep", "solve_sweep", "build", "analysis", "gram", "panel_update", "panel_factor", "residual",
-           "step1")
+           "step1", "fused_sweep")
 
 
 def parse():
@@ -104,11 +104,11 @@ def run_form(name, w, args, pk, torch, cache):
     def step():
         if full:
             pk.enkf_build_vd(g["XB"], g["obs"], g["y"], g["E"], g["V"], g["D"])
-        plan.refactor(g["r"], g["V"])
+        # factorisation + solve in one call (plain: one level loop over U and Z)
         if refine:
-            _, last["info"] = plan.solve(g["D"], g["Z"], info=True)
+            _, last["info"] = plan.factor_solve(g["r"], g["V"], g["D"], g["Z"], info=True)
         else:
-            plan.solve(g["D"], g["Z"])
+            plan.factor_solve(g["r"], g["V"], g["D"], g["Z"])
         if full:
             plan.analysis(g["XB"], g["Z"], g["XA"])
 
@@ -162,11 +162,11 @@ def run_form(name, w, args, pk, torch, cache):
 def roofline_of(form, name):
     k = form["kernels"]
     if form["algo"] == "plain":
-        c = k["solve_sweep"]
+        c = k["fused_sweep"]
         ach = c["alg_bytes_per_launch"] / (c["avg_launch_us"] * 1e-6) / 1e9
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"level_kernel ({name}: solve sweep, one launch per level)",
+                "kernel": f"level_kernel ({name}: fused factor + solve sweep, one launch per level)",
                 "avg_launch_us": c["avg_launch_us"], "alg_bytes_per_launch": c["alg_bytes_per_launch"]}
     c = k["gram"]
     ach = c["alg_flops_per_launch"] / (c["avg_launch_us"] * 1e-6) / 1e12

@@ -152,6 +152,19 @@ enkf_status enkf_sm_solve(enkf_sm_plan plan, int32_t nrhs, const void* D, int64_
                           enkf_sm_info* info);
 
 /*
+ * enkf_sm_refactor followed by enkf_sm_solve, as one pass of the level loop
+ * of Section 3.3 (Steps 1-2): for the plain algorithm, Step 1 for V and D,
+ * then one launch per level k that forms gamma_k (eq. gamma-value) and
+ * updates the U columns k+1..N and every Z column together (eq. SM-step-2),
+ * so each level reads and writes the active columns of both once. Leaves the
+ * same factor as enkf_sm_refactor (later enkf_sm_solve calls reuse it).
+ * Arguments and errors as the two calls; the blocked algorithm runs them in
+ * sequence. Allocates nothing.
+ */
+enkf_status enkf_sm_factor_solve(enkf_sm_plan plan, const double* r, const void* V, int64_t ldv, int32_t nrhs,
+                                 const void* D, int64_t ldd, void* Z, int64_t ldz, enkf_sm_info* info);
+
+/*
  * Analysis update X^A = X^B + S (V^T Z) with S = (X^B - xbar 1^T)/sqrt(N-1)
  * (Section 3.1), using the plan's V. XB and XA are n_state x N (ldx, ldxa >=
  * n_state) in the plan's dtype; Z is n_obs x N (ldz >= n_obs). XA must not
@@ -190,7 +203,8 @@ enkf_status enkf_sm_get_pivots(enkf_sm_plan plan, double* gamma_host, int32_t* p
  * Classes: 0 factor level sweeps (plain), 1 solve level sweeps (plain),
  * 2 build, 3 analysis update, 4 split-K products, 5 panel updates (blocked),
  * 6 panel factorisations (blocked), 7 FP64 residuals (refinement),
- * 8 Step 1 (with the plain form's first look-ahead products).
+ * 8 Step 1 (with the plain form's first look-ahead products), 9 level sweeps
+ * of a fused factorisation + solve (plain).
  */
 enkf_status enkf_sm_set_timing(enkf_sm_plan plan, int32_t enable);
 enkf_status enkf_sm_get_timing(enkf_sm_plan plan, int32_t kernel_class, double* total_ms, int64_t* launches,

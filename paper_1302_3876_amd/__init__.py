@@ -29,7 +29,8 @@ ENKF_FLAG_PIVOT = 0x1
 STATUS = {0: "ENKF_SUCCESS", 1: "ENKF_ERR_INVALID_ARG", 2: "ENKF_ERR_NOT_SPD", 3: "ENKF_ERR_NO_CONVERGENCE",
           4: "ENKF_ERR_HIP", 5: "ENKF_ERR_OUT_OF_MEMORY", 6: "ENKF_ERR_NOT_SUPPORTED"}
 KERNEL_CLASSES = {"factor_sweep": 0, "solve_sweep": 1, "build": 2, "analysis": 3, "gram": 4,
-                  "panel_update": 5, "panel_factor": 6, "residual": 7, "step1": 8}
+                  "panel_update": 5, "panel_factor": 6, "residual": 7, "step1": 8,
+                  "fused_sweep": 9}
 
 
 class EnkfError(RuntimeError):
@@ -77,6 +78,7 @@ def lib():
     L.enkf_sm_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SmDesc), vp, vp, i64, vp]
     L.enkf_sm_solve.argtypes = [vp, i32, vp, i64, vp, i64, ctypes.POINTER(SmInfo)]
     L.enkf_sm_refactor.argtypes = [vp, vp, vp, i64]
+    L.enkf_sm_factor_solve.argtypes = [vp, vp, vp, i64, i32, vp, i64, vp, i64, ctypes.POINTER(SmInfo)]
     L.enkf_analysis.argtypes = [vp, i64, vp, i64, vp, i64, vp, i64]
     L.enkf_analysis_ex.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, vp, i64]
     L.enkf_sm_get_info.argtypes = [vp, ctypes.POINTER(SmInfo)]
@@ -95,7 +97,7 @@ def lib():
     L.enkf_status_string.restype = ctypes.c_char_p
     L.enkf_last_error_message.argtypes = []
     L.enkf_last_error_message.restype = ctypes.c_char_p
-    for name in ("enkf_sm_validate_desc", "enkf_build_vd", "enkf_sm_init", "enkf_sm_refactor", "enkf_sm_solve", "enkf_analysis",
+    for name in ("enkf_sm_validate_desc", "enkf_build_vd", "enkf_sm_init", "enkf_sm_refactor", "enkf_sm_factor_solve", "enkf_sm_solve", "enkf_analysis",
                  "enkf_analysis_ex", "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_set_timing", "enkf_sm_get_timing",
                  "enkf_local_init", "enkf_local_analysis", "enkf_local_sync"):
         getattr(L, name).restype = ctypes.c_int
@@ -242,6 +244,22 @@ class Plan:
         inf = SmInfo() if info else None
         _check(lib().enkf_sm_solve(self._handle, D.shape[1], pD, ldd, pZ, ldz,
                                    ctypes.byref(inf) if info else None), "enkf_sm_solve")
+        return (Z, inf.as_dict()) if info else Z
+
+    def factor_solve(self, r, V, D, Z=None, info: bool = False):
+        """refactor(r, V) and solve(D) in one level loop (enkf_sm_factor_solve)."""
+        torch = _torch()
+        pV, ldv = _mat(V, "V", self.dtype)
+        if tuple(V.shape) != (self.n_obs, self.n_ens):
+            raise ValueError("factor_solve: V shape differs from the plan's")
+        pD, ldd = _mat(D, "D", self.dtype)
+        if Z is None:
+            Z = colmajor(D.shape[0], D.shape[1], D.dtype, D.device)
+        pZ, ldz = _mat(Z, "Z", self.dtype)
+        inf = SmInfo() if info else None
+        _check(lib().enkf_sm_factor_solve(self._handle, _vec(r, "r", torch.float64), pV, ldv, D.shape[1], pD, ldd,
+                                          pZ, ldz, ctypes.byref(inf) if info else None), "enkf_sm_factor_solve")
+        self._r, self._V = r, V
         return (Z, inf.as_dict()) if info else Z
 
     def analysis(self, XB, Z, XA=None):

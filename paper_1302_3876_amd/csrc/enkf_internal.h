@@ -28,7 +28,8 @@ enum KernelClass : int {
   KC_PANEL_FACTOR = 6, // blocked: b x b LDL^T and solves
   KC_RESIDUAL = 7,     // FP64 residual of the refinement
   KC_STEP1 = 8,        // Step 1 (R^{-1} V, R^{-1} D) and the plain form's first products
-  KC_COUNT = 9
+  KC_FUSED_SWEEP = 9,  // plain: U- and Z-updates of one level in one launch (factor + solve)
+  KC_COUNT = 10
 };
 
 void set_error(const std::string& msg);
@@ -90,6 +91,7 @@ struct LevelArgs {
   const double* r;                      // Step 1: diag(R)
   const void* src; int64_t lds;         // Step 1: V or D
   double* part_out;                     // this launch's partials ([m][nb])
+  void* dst; int64_t ldo;               // if set, the updated columns go here instead of back to X
   unsigned* status;                     // device status word
 };
 

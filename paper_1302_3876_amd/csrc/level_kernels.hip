@@ -2,7 +2,9 @@
 // kernel launch per level, for gfx950.
 //
 // A launch updates m active columns x_q of X (the U columns k+1..N during
-// the factorisation, or every Z column during a solve):
+// the factorisation, every Z column during a solve, or both at once when
+// the factorisation and a solve run together, as in the level loop of
+// Section 3.3):
 //     Step 1 (eq. SM-step-1):  x_q = src_q / r
 //     level k (eq. SM-step-2): x_q <- x_q - h_k c_q,  h_k = u_k^{(k-1)} / gamma_k,
 //                              c_q = v_k^T x_q  (reduced by the previous launch)
@@ -35,46 +37,56 @@ template <> struct VecT<float, 4> { typedef float type __attribute__((ext_vector
 template <> struct VecT<double, 1> { typedef double type; };
 template <> struct VecT<float, 1> { typedef float type; };
 
+// Loads and stores of VW consecutive rows. The launcher picks VW > 1 only
+// when columns are 16-byte aligned and VW divides n, so a vector is wholly
+// inside or wholly outside the rows; callers pass a valid row index (rows
+// past n are redirected to row 0 and their values never stored), so loads
+// carry no branches and all of a block's loads are in flight together.
 template <typename T, int VW>
-__device__ __forceinline__ void load_rows(const T* __restrict__ p, int64_t row, int64_t n, T (&v)[VW]) {
-  if (row + VW <= n) {
-    typedef typename VecT<T, VW>::type vt;
-    vt x = *reinterpret_cast<const vt*>(p + row);
-    if constexpr (VW == 1) {
-      v[0] = x;
-    } else {
-#pragma unroll
-      for (int e = 0; e < VW; ++e) v[e] = x[e];
-    }
+__device__ __forceinline__ void load_vec(const T* __restrict__ p, int64_t row, T (&v)[VW]) {
+  typedef typename VecT<T, VW>::type vt;
+  const vt x = *reinterpret_cast<const vt*>(p + row);
+  if constexpr (VW == 1) {
+    v[0] = x;
   } else {
 #pragma unroll
-    for (int e = 0; e < VW; ++e) v[e] = (row + e < n) ? p[row + e] : T(0);
+    for (int e = 0; e < VW; ++e) v[e] = x[e];
   }
 }
 
 template <typename T, int VW>
-__device__ __forceinline__ void store_rows(T* __restrict__ p, int64_t row, int64_t n, const T (&v)[VW]) {
-  if (row + VW <= n) {
-    typedef typename VecT<T, VW>::type vt;
-    vt x;
-    if constexpr (VW == 1) {
-      x = v[0];
-    } else {
-#pragma unroll
-      for (int e = 0; e < VW; ++e) x[e] = v[e];
-    }
-    *reinterpret_cast<vt*>(p + row) = x;
+__device__ __forceinline__ void store_vec(T* __restrict__ p, int64_t row, const T (&v)[VW]) {
+  typedef typename VecT<T, VW>::type vt;
+  vt x;
+  if constexpr (VW == 1) {
+    x = v[0];
   } else {
 #pragma unroll
-    for (int e = 0; e < VW; ++e)
-      if (row + e < n) p[row + e] = v[e];
+    for (int e = 0; e < VW; ++e) x[e] = v[e];
   }
+  *reinterpret_cast<vt*>(p + row) = x;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;
+}
+
+// Lane-strided sum of nb partials: lane l adds p[l], p[l+64], ... in that
+// order (loads issued four at a time).
+__device__ __forceinline__ double lane_strided_sum(const double* __restrict__ p, int nb, int lane) {
+  double s = 0.0;
+  int b = lane;
+  for (; b + 3 * kWave < nb; b += 4 * kWave) {
+    const double x0 = p[b], x1 = p[b + kWave], x2 = p[b + 2 * kWave], x3 = p[b + 3 * kWave];
+    s += x0;
+    s += x1;
+    s += x2;
+    s += x3;
+  }
+  for (; b < nb; b += kWave) s += p[b];
+  return s;
 }
 
 // Sum of one value per thread over the block, returned to every thread, in a
@@ -103,18 +115,45 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
   const int t = threadIdx.x;
   const int lane = t % kWave, wave = t / kWave;
   T* __restrict__ X = static_cast<T*>(a.X);
+  T* __restrict__ Out = a.dst ? static_cast<T*>(a.dst) : X;
+  const int64_t ldo = a.dst ? a.ldo : a.ldx;
 
-  // Products c_q = v_k^T x_q of this block's columns (and of the pivot
-  // column when forming gamma_k), from the previous launch's partials.
+  int64_t rows[RPT], rowc[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    rows[r] = row_base + ((int64_t)r * LV_THREADS + t) * VW;
+    rowc[r] = rows[r] < n ? rows[r] : 0;
+  }
+
+  // 1. Every load of the block first: the active columns (a column past the
+  //    last reads the last one and is not stored; the source of Step 1 may
+  //    be the destination itself), u_k and v_{k+1}.
+  T xv[COLS][RPT][VW];
+  const T* __restrict__ src = STEP1 ? static_cast<const T*>(a.src) : X;
+  const int64_t lds = STEP1 ? a.lds : a.ldx;
+#pragma unroll
+  for (int c = 0; c < COLS; ++c) {
+    const T* __restrict__ col = src + (int64_t)min(col0 + c, a.m - 1) * lds;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) load_vec<T, VW>(col, rowc[r], xv[c][r]);
+  }
+  T uv[RPT][VW], vv[RPT][VW];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    if constexpr (!STEP1) load_vec<T, VW>(static_cast<const T*>(a.uk), rowc[r], uv[r]);
+    if constexpr (LOOKAHEAD) load_vec<T, VW>(static_cast<const T*>(a.vnext), rowc[r], vv[r]);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // 2. Products c_q = v_k^T x_q of this block's columns (and of the pivot
+  //    column when forming gamma_k), from the previous launch's partials.
   __shared__ double cq_s[COLS];
   __shared__ double gam_s;
   if constexpr (!STEP1) {
     const int nred = ncol + (OWN_GAMMA ? 1 : 0);
     for (int c = wave; c < nred; c += LV_WAVES) {
       const int pc = (c < ncol) ? (col0 + c + a.prev_off) : 0;
-      const double* __restrict__ p = a.prev + (int64_t)pc * nb;
-      double sacc = 0.0;
-      for (int b = lane; b < nb; b += kWave) sacc += p[b];
+      double sacc = lane_strided_sum(a.prev + (int64_t)pc * nb, nb, lane);
       sacc = wave_sum(sacc);
       if (lane == 0) {
         if (c < ncol) cq_s[c] = sacc;
@@ -124,7 +163,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
     __syncthreads();
   }
 
-  // Per-row factors: 1/r_i (Step 1) or h_k[i] = u_k[i] / gamma_k (level).
+  // 3. Per-row factors: 1/r_i (Step 1) or h_k[i] = u_k[i] / gamma_k (level).
   double hrow[RPT][VW];
   double vn[RPT][VW];
   double inv_gamma = 0.0;
@@ -143,65 +182,41 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
   }
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int64_t row = row_base + ((int64_t)r * LV_THREADS + t) * VW;
+    const bool ok = rows[r] < n;
     if constexpr (STEP1) {
 #pragma unroll
       for (int e = 0; e < VW; ++e) {
-        double rv = (row + e < n) ? a.r[row + e] : 1.0;
-        if (!(rv > 0.0) || !__builtin_isfinite(rv)) atomicOr(a.status, kStatusNotSpd);
-        hrow[r][e] = 1.0 / rv;
+        const double rv = a.r[rowc[r] + e];
+        if (ok && (!(rv > 0.0) || !__builtin_isfinite(rv))) atomicOr(a.status, kStatusNotSpd);
+        hrow[r][e] = ok ? 1.0 / rv : 0.0;
       }
     } else {
-      T u[VW];
-      if (row < n) load_rows<T, VW>(static_cast<const T*>(a.uk), row, n, u);
 #pragma unroll
-      for (int e = 0; e < VW; ++e) hrow[r][e] = (row < n) ? (double)u[e] * inv_gamma : 0.0;
+      for (int e = 0; e < VW; ++e) hrow[r][e] = ok ? (double)uv[r][e] * inv_gamma : 0.0;
     }
     if constexpr (LOOKAHEAD) {
-      T v[VW];
-      if (row < n) load_rows<T, VW>(static_cast<const T*>(a.vnext), row, n, v);
 #pragma unroll
-      for (int e = 0; e < VW; ++e) vn[r][e] = (row < n) ? (double)v[e] : 0.0;
+      for (int e = 0; e < VW; ++e) vn[r][e] = ok ? (double)vv[r][e] : 0.0;
     }
   }
 
-  // Load every active value of this block first (columns never overlap; the
-  // source of Step 1 may be the destination itself).
-  T xv[COLS][RPT][VW];
-  const T* __restrict__ src = STEP1 ? static_cast<const T*>(a.src) : X;
-  const int64_t lds = STEP1 ? a.lds : a.ldx;
-#pragma unroll
-  for (int c = 0; c < COLS; ++c) {
-    if (c < ncol) {
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int64_t row = row_base + ((int64_t)r * LV_THREADS + t) * VW;
-        if (row < n) load_rows<T, VW>(src + (int64_t)(col0 + c) * lds, row, n, xv[c][r]);
-      }
-    }
-  }
-
+  // 4. Update, look-ahead products, stores.
   double acc[COLS];
 #pragma unroll
   for (int c = 0; c < COLS; ++c) {
     acc[c] = 0.0;
-    if (c < ncol) {
-      double cq = 0.0;
-      if constexpr (!STEP1) cq = cq_s[c];
+    double cq = 0.0;
+    if constexpr (!STEP1) cq = (c < ncol) ? cq_s[c] : 0.0;
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int64_t row = row_base + ((int64_t)r * LV_THREADS + t) * VW;
-        if (row < n) {
+    for (int r = 0; r < RPT; ++r) {
 #pragma unroll
-          for (int e = 0; e < VW; ++e) {
-            double x = (double)xv[c][r][e];
-            x = STEP1 ? x * hrow[r][e] : x - hrow[r][e] * cq;
-            xv[c][r][e] = (T)x;
-            if constexpr (LOOKAHEAD) acc[c] += vn[r][e] * (double)xv[c][r][e];
-          }
-          store_rows<T, VW>(X + (int64_t)(col0 + c) * a.ldx, row, n, xv[c][r]);
-        }
+      for (int e = 0; e < VW; ++e) {
+        double x = (double)xv[c][r][e];
+        x = STEP1 ? x * hrow[r][e] : x - hrow[r][e] * cq;
+        xv[c][r][e] = (T)x;
+        if constexpr (LOOKAHEAD) acc[c] += vn[r][e] * (double)xv[c][r][e];
       }
+      if (c < ncol && rows[r] < n) store_vec<T, VW>(Out + (int64_t)(col0 + c) * ldo, rows[r], xv[c][r]);
     }
   }
   if constexpr (!LOOKAHEAD) return;
@@ -226,9 +241,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
 // kernels sum it (lane-strided, then the shuffle tree).
 __global__ __launch_bounds__(kWave) void gamma_kernel(const double* __restrict__ part, int nb, int col,
                                                       double* __restrict__ gamma_out, unsigned* status) {
-  const double* p = part + (int64_t)col * nb;
-  double sacc = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kWave) sacc += p[b];
+  double sacc = lane_strided_sum(part + (int64_t)col * nb, nb, threadIdx.x);
   sacc = wave_sum(sacc);
   if (threadIdx.x == 0) {
     const double gam = 1.0 + sacc;

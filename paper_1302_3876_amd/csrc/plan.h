@@ -22,7 +22,7 @@ struct Plan {
   // workspace (one allocation, carved into the pieces below)
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  void* U = nullptr;            // plain factor: column k = u_k^{(k-1)}
+  void* U = nullptr;            // plain factor: column k = u_k^{(k-1)}; then max_nrhs columns of Z (fused)
   int64_t ldu = 0;
   double* gamma = nullptr;      // N pivots
   double* part[2] = {nullptr, nullptr};  // level sweeps: per-block partial products, alternating
@@ -52,6 +52,8 @@ struct Plan {
   enkf_status create(const enkf_sm_desc& d, const double* r, const void* V, int64_t ldv, hipStream_t s);
   enkf_status factor();
   enkf_status solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, enkf_sm_info* info);
+  // factor() and solve() together (plain: one launch per level for U and Z)
+  enkf_status factor_solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, enkf_sm_info* info);
   enkf_status analysis(int64_t n_state, enkf_dtype x_dtype, enkf_math math, const void* XB, int64_t ldx,
                        const void* Z, int64_t ldz, void* XA, int64_t ldxa);
   enkf_status get_info(enkf_sm_info* info);
@@ -63,6 +65,7 @@ struct Plan {
  private:
   enkf_status factor_plain();
   enkf_status solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
+  enkf_status factor_solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
   enkf_status factor_blocked();
   // Z = (R + V V^T)^{-1} D with the blocked factor, all in the working type.
   enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);

@@ -81,7 +81,9 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
 
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  const size_t oU = take((size_t)ldu * N * wes);
+  // plain: U is followed by max_nrhs columns that hold Z during a fused
+  // factorisation + solve, so one launch per level covers [U_{>k}, Z]
+  const size_t oU = take((size_t)ldu * (N + (blocked ? 0 : max_nrhs)) * wes);
   const size_t oGamma = take(sizeof(double) * N);
   const size_t oStat = take(sizeof(unsigned) * 4);
   const size_t oG = take(sizeof(double) * (size_t)N * mcols);
@@ -101,7 +103,7 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   const size_t oBt = take(nn_bt_bytes(N, mcols));
   size_t oP0 = 0, oP1 = 0, oMinv = 0, oPbuf = 0, oQbuf = 0, oVw = 0, oZw = 0, oRho = 0, oNorm = 0;
   if (!blocked) {
-    const size_t part_elems = (size_t)level_row_blocks(d.dtype, 1, n) * mcols;
+    const size_t part_elems = (size_t)level_row_blocks(d.dtype, 1, n) * (N + max_nrhs);
     oP0 = take(sizeof(double) * part_elems);
     oP1 = take(sizeof(double) * part_elems);
   } else {
@@ -157,8 +159,8 @@ enkf_status Plan::factor() { return desc.algo == ENKF_SM_PLAIN ? factor_plain() 
 enkf_status Plan::factor_plain() {
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
-  const int vw = (vec_ok(U, ldu, level_vw(desc.dtype), es) && vec_ok(V, ldv, level_vw(desc.dtype), es))
-                     ? level_vw(desc.dtype) : 1;
+  const int w = level_vw(desc.dtype);
+  const int vw = (n % w == 0 && vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es)) ? w : 1;
   const int nb = level_row_blocks(desc.dtype, vw, n);
   // Step 1 for V: U0 = R^{-1} V and the products v_1^T u_j^{(0)}.
   LevelArgs a{};
@@ -211,8 +213,8 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
   const int N = desc.n_ens;
   if (nrhs == 0) return ENKF_SUCCESS;
   const int w = level_vw(desc.dtype);
-  const int vw =
-      (vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es) && vec_ok(D, ldd, w, es) && vec_ok(Z, ldz, w, es)) ? w : 1;
+  const int vw = (n % w == 0 && vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es) && vec_ok(D, ldd, w, es) &&
+                  vec_ok(Z, ldz, w, es)) ? w : 1;
   LevelArgs a{};
   a.n = n;
   a.vw = vw;
@@ -254,6 +256,81 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
     if (st != ENKF_SUCCESS) return st;
   }
   return ENKF_SUCCESS;
+}
+
+// Factorisation and solve in one level loop (Section 3.3): Step 1 for V and
+// for D, then per level k one launch over [U columns k+1..N-1, Z] that forms
+// gamma_k, applies h_k to every active column and leaves the products with
+// v_{k+1}. Z lives in the columns after U during the loop; the last level
+// writes it to the caller's buffer. Leaves the same factor as factor_plain.
+enkf_status Plan::factor_solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz) {
+  const int64_t n = desc.n_obs;
+  const int N = desc.n_ens;
+  if (nrhs == 0) return factor_plain();
+  const int w = level_vw(desc.dtype);
+  const int vw = (n % w == 0 && vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es) && vec_ok(D, ldd, w, es) &&
+                  vec_ok(Z, ldz, w, es)) ? w : 1;
+  const int nb = level_row_blocks(desc.dtype, vw, n);
+  char* Ub = static_cast<char*>(U);
+  void* Zb = Ub + (size_t)N * ldu * es;
+  for (int half = 0; half < 2; ++half) {
+    LevelArgs a{};
+    a.n = n;
+    a.vw = vw;
+    a.status = status;
+    a.X = half == 0 ? U : Zb;
+    a.ldx = ldu;
+    a.m = half == 0 ? N : nrhs;
+    a.src = half == 0 ? V : D;
+    a.lds = half == 0 ? ldv : ldd;
+    a.r = r;
+    a.vnext = vcol(0);
+    a.part_out = part[0] + (half == 0 ? 0 : (size_t)N * nb);
+    double by, fl;
+    sweep_model(n, a.m, es, true, true, &by, &fl);
+    TimedLaunch tl(&timing, stream, KC_STEP1, by, fl);
+    enkf_status st = launch_level(desc.dtype, a, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  for (int k = 0; k < N; ++k) {
+    LevelArgs b{};
+    b.n = n;
+    b.vw = vw;
+    b.status = status;
+    b.X = Ub + (size_t)(k + 1) * ldu * es;
+    b.ldx = ldu;
+    b.m = N - k - 1 + nrhs;
+    b.uk = Ub + (size_t)k * ldu * es;
+    b.gamma_out = gamma + k;
+    b.prev = part[k & 1];
+    b.prev_m = N - k + nrhs;
+    b.prev_off = 1;
+    b.vnext = (k + 1 < N) ? vcol(k + 1) : nullptr;
+    b.part_out = part[(k + 1) & 1];
+    if (k + 1 == N) {
+      b.dst = Z;
+      b.ldo = ldz;
+    }
+    double by, fl;
+    sweep_model(n, b.m, es, false, b.vnext != nullptr, &by, &fl);
+    TimedLaunch tl(&timing, stream, KC_FUSED_SWEEP, by, fl);
+    enkf_status st = launch_level(desc.dtype, b, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  return ENKF_SUCCESS;
+}
+
+enkf_status Plan::factor_solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, enkf_sm_info* info) {
+  if (desc.algo != ENKF_SM_PLAIN) {
+    enkf_status st = factor();
+    if (st != ENKF_SUCCESS) return st;
+    return solve(nrhs, D, ldd, Z, ldz, info);
+  }
+  enkf_status st = factor_solve_plain(nrhs, D, ldd, Z, ldz);
+  last.refine_iters = 0;
+  last.rel_residual = -1.0;
+  if (st != ENKF_SUCCESS) return st;
+  return info ? get_info(info) : ENKF_SUCCESS;
 }
 
 // ------------------------------------------------------------------ blocked

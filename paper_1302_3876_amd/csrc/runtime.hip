@@ -189,6 +189,27 @@ enkf_status enkf_sm_solve(enkf_sm_plan plan, int32_t nrhs, const void* D, int64_
   return p->solve(nrhs, D, ldd, Z, ldz, info);
 }
 
+enkf_status enkf_sm_factor_solve(enkf_sm_plan plan, const double* r, const void* V, int64_t ldv, int32_t nrhs,
+                                 const void* D, int64_t ldd, void* Z, int64_t ldz, enkf_sm_info* info) {
+  if (!plan) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: plan is NULL");
+  if (!r || !V) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: r or V is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (ldv < p->desc.n_obs) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: ldv < n_obs");
+  if (nrhs < 0 || nrhs > p->max_nrhs) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: nrhs outside [0, max_nrhs]");
+  if (nrhs > 0) {
+    if (!D || !Z) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: D or Z is NULL");
+    if (ldd < p->desc.n_obs || ldz < p->desc.n_obs)
+      return fail(ENKF_ERR_INVALID_ARG, "factor_solve: leading dimension < n_obs");
+    if (D == Z && ldd != ldz) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: Z aliases D with a different leading dimension");
+  }
+  p->r = r;
+  p->V = V;
+  p->ldv = ldv;
+  enkf_status st = p->clear_status();
+  if (st != ENKF_SUCCESS) return st;
+  return p->factor_solve(nrhs, D, ldd, Z, ldz, info);
+}
+
 static enkf_status analysis_checks(Plan* p, int64_t n_state, enkf_dtype x_dtype, const void* XB, int64_t ldx,
                                    const void* Z, int64_t ldz, void* XA, int64_t ldxa) {
   if (n_state < 1) return fail(ENKF_ERR_INVALID_ARG, "analysis: n_state must be >= 1");

@@ -75,6 +75,7 @@ def test_null_arguments_rejected_without_gpu():
     assert lib.enkf_sm_init(None, ctypes.byref(_desc()), None, None, 100, None) == 1
     assert lib.enkf_sm_init(ctypes.byref(h), ctypes.byref(_desc()), None, None, 100, None) == 1
     assert lib.enkf_sm_solve(None, 1, None, 1, None, 1, None) == 1
+    assert lib.enkf_sm_factor_solve(None, None, None, 1, 1, None, 1, None, 1, None) == 1
     assert lib.enkf_analysis(None, 1, None, 1, None, 1, None, 1) == 1
     assert lib.enkf_build_vd(10, 1, 0, None, 10, None, 5, None, None, 5, None, None, 5, None) == 1
     assert lib.enkf_build_vd(10, 4, 0, None, 10, None, 5, None, None, 5, None, None, 5, None) == 1

@@ -46,6 +46,48 @@ def test_solve_fp32_matches_oracle(n, N):
     assert rel(host(Z), ref["Z"]) < 1e-4
 
 
+@pytest.mark.parametrize("n,N,nrhs", [(1, 1, 1), (5, 3, 2), (4099, 33, 5), (16384, 96, 96), (70001, 40, 40),
+                                      (3, 50, 50), (1002, 7, 11)])
+def test_fused_factor_solve_matches_oracle_and_split_path(n, N, nrhs):
+    """One level loop over [U, Z] (enkf_sm_factor_solve): parity with the
+    oracle, and bitwise the same Z and pivots as refactor + solve (every
+    column's products are summed in the same order in both)."""
+    import torch
+    print(f"fused fp64 n={n} N={N} nrhs={nrhs}", flush=True)
+    pk = _pk()
+    r, V, D = synth.small_vd(n, N, seed=3000 + n + N, nrhs=nrhs)
+    rd, Vd, Dd = dev(r), dev(V), dev(D)
+    plan = pk.Plan(rd, Vd, max_nrhs=max(nrhs, N))
+    Zs = plan.solve(Dd)
+    gs, _ = plan.pivots()
+    Zf, info = plan.factor_solve(rd, Vd, Dd, info=True)
+    torch.cuda.synchronize()
+    gf, _ = plan.pivots()
+    assert info["device_status"] == 0
+    assert np.array_equal(host(Zf), host(Zs))
+    assert np.array_equal(gf, gs)
+    fp64_gate(r, V, D, host(Zf), oracle.sm_solve(r, V, D)["Z"])
+    # the factor it leaves serves later solves
+    assert np.array_equal(host(plan.solve(Dd)), host(Zs))
+
+
+def test_fused_factor_solve_fp32_alias_and_zero_rhs():
+    import torch
+    pk = _pk()
+    n, N = 65536, 64
+    r, V, D = synth.small_vd(n, N, seed=77, r_range=(0.005, 0.02), v_scale=0.3)
+    rd, Vd = dev(r), dev(V, torch.float32)
+    plan = pk.Plan(rd, Vd)
+    Zs = host(plan.solve(dev(D, torch.float32)))
+    Dd = dev(D, torch.float32)
+    Zf = plan.factor_solve(rd, Vd, Dd, Dd)    # Z aliases D
+    torch.cuda.synchronize()
+    assert np.array_equal(host(Zf), Zs)
+    empty = pk.colmajor(n, 0, torch.float32)
+    plan.factor_solve(rd, Vd, empty, empty)   # factorisation only
+    assert np.array_equal(host(plan.solve(dev(D, torch.float32))), Zs)
+
+
 def test_unaligned_leading_dimension_and_alias():
     import torch
     pk = _pk()
