@@ -55,13 +55,14 @@ FORMS = {
     # name: (algo, storage, math, refine)
     "plain_f64": ("plain", "f64", "f64", 0),
     "plain_f32": ("plain", "f32", "f32", 0),
+    "plain_f64_pivot": ("plain", "f64", "f64", 0),
     "blocked_f64": ("blocked", "f64", "f64", 0),
     "blocked_f32": ("blocked", "f32", "f32", 0),
     "mixed_f32": ("blocked", "f64", "f32", 8),
     "mixed_bf16x3": ("blocked", "f64", "bf16x3", 12),
     "mixed_f16x2": ("blocked", "f64", "f16x2", 12),
 }
-DEFAULT_FORMS = {"c2": ["plain_f64", "plain_f32", "blocked_f64", "mixed_f32"],
+DEFAULT_FORMS = {"c2": ["plain_f64", "plain_f32", "blocked_f64", "mixed_f32", "plain_f64_pivot"],
                  "c3": ["blocked_f64", "mixed_f32", "mixed_bf16x3", "mixed_f16x2", "plain_f64"]}
 
 
@@ -98,7 +99,8 @@ def run_form(name, w, args, pk, torch, cache):
     # mixed forms refine until the FP64 residual is <= 1e-10 (synchronous
     # check per refinement step), at most `refine` steps
     tol = 1e-10 if refine else 0.0
-    plan = pk.Plan(g["r"], g["V"], algo=algo, math=math, block=block, refine_max_iter=refine, refine_tol=tol)
+    plan = pk.Plan(g["r"], g["V"], algo=algo, math=math, block=block, refine_max_iter=refine, refine_tol=tol,
+                   pivot=name.endswith("_pivot"))
     last = {}
 
     def step():

@@ -92,6 +92,12 @@ struct LevelArgs {
   const void* src; int64_t lds;         // Step 1: V or D
   double* part_out;                     // this launch's partials ([m][nb])
   void* dst; int64_t ldo;               // if set, the updated columns go here instead of back to X
+  // pivoting: active column q is column colmap[q] of X (and partial slot
+  // colmap[q]); u_k = uk + (*uk_idx) ldu_idx and v_{k+1} = vnext + (*vn_idx)
+  // ldv_idx, read on the device (the pivots are chosen on the device)
+  const int32_t* colmap;
+  const int32_t* uk_idx; int64_t ldu_idx;
+  const int32_t* vn_idx; int64_t ldv_idx;
   unsigned* status;                     // device status word
 };
 
@@ -101,6 +107,24 @@ enkf_status launch_gamma_from_partials(const double* part, int nb, int col, doub
                                        hipStream_t s);
 int level_row_blocks(enkf_dtype dt, int vw, int64_t n);
 int level_vw(enkf_dtype dt);
+
+// ---------------------------------------------------------------- pivoting
+struct PivotArgs {
+  int init;                 // 1: from the diagonal partials; 0: before level k
+  int k, N, nz;             // level, members, Z columns appended to the active list
+  const double* part; int nb;   // partials [slot][nb]
+  int32_t* perm;            // perm[k] = column used at level k
+  double* gamma;            // gamma[k]
+  double* gcur;             // candidate pivots (N)
+  double* cbuf;             // c_i of this level (N)
+  const int32_t* rem_in;    // remaining columns before level k (N - k)
+  int32_t* rem_out;         // remaining after level k (N - k - 1), or 0..N-1 (init)
+  int32_t* act_out;         // active list of level k (N - k - 1 + nz)
+  unsigned* status;
+};
+enkf_status launch_diag_partials(enkf_dtype dt, int64_t n, int N, const void* V, int64_t ldv, const double* r,
+                                 int nb, double* part, hipStream_t s);
+enkf_status launch_pivot(const PivotArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- build
 enkf_status launch_build_vd(enkf_dtype dt, int64_t n_state, int n_ens, const void* XB, int64_t ldx,

@@ -117,6 +117,13 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
   T* __restrict__ X = static_cast<T*>(a.X);
   T* __restrict__ Out = a.dst ? static_cast<T*>(a.dst) : X;
   const int64_t ldo = a.dst ? a.ldo : a.ldx;
+  const int32_t* __restrict__ cmap = a.colmap;
+  // column (of X, and partial slot) of active column q
+  auto phys = [&](int q) -> int { return cmap ? cmap[q] : q; };
+  const T* __restrict__ ukp = static_cast<const T*>(a.uk);
+  if (!STEP1 && a.uk_idx) ukp += (int64_t)(*a.uk_idx) * a.ldu_idx;
+  const T* __restrict__ vnp = static_cast<const T*>(a.vnext);
+  if (LOOKAHEAD && a.vn_idx) vnp += (int64_t)(*a.vn_idx) * a.ldv_idx;
 
   int64_t rows[RPT], rowc[RPT];
 #pragma unroll
@@ -133,15 +140,15 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
   const int64_t lds = STEP1 ? a.lds : a.ldx;
 #pragma unroll
   for (int c = 0; c < COLS; ++c) {
-    const T* __restrict__ col = src + (int64_t)min(col0 + c, a.m - 1) * lds;
+    const T* __restrict__ col = src + (int64_t)phys(min(col0 + c, a.m - 1)) * lds;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) load_vec<T, VW>(col, rowc[r], xv[c][r]);
   }
   T uv[RPT][VW], vv[RPT][VW];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    if constexpr (!STEP1) load_vec<T, VW>(static_cast<const T*>(a.uk), rowc[r], uv[r]);
-    if constexpr (LOOKAHEAD) load_vec<T, VW>(static_cast<const T*>(a.vnext), rowc[r], vv[r]);
+    if constexpr (!STEP1) load_vec<T, VW>(ukp, rowc[r], uv[r]);
+    if constexpr (LOOKAHEAD) load_vec<T, VW>(vnp, rowc[r], vv[r]);
   }
   __builtin_amdgcn_sched_barrier(0);
 
@@ -152,7 +159,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
   if constexpr (!STEP1) {
     const int nred = ncol + (OWN_GAMMA ? 1 : 0);
     for (int c = wave; c < nred; c += LV_WAVES) {
-      const int pc = (c < ncol) ? (col0 + c + a.prev_off) : 0;
+      const int pc = (c < ncol) ? (cmap ? cmap[col0 + c] : col0 + c + a.prev_off) : 0;
       double sacc = lane_strided_sum(a.prev + (int64_t)pc * nb, nb, lane);
       sacc = wave_sum(sacc);
       if (lane == 0) {
@@ -216,7 +223,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
         xv[c][r][e] = (T)x;
         if constexpr (LOOKAHEAD) acc[c] += vn[r][e] * (double)xv[c][r][e];
       }
-      if (c < ncol && rows[r] < n) store_vec<T, VW>(Out + (int64_t)(col0 + c) * ldo, rows[r], xv[c][r]);
+      if (c < ncol && rows[r] < n) store_vec<T, VW>(Out + (int64_t)phys(col0 + c) * ldo, rows[r], xv[c][r]);
     }
   }
   if constexpr (!LOOKAHEAD) return;
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
     double sacc = 0.0;
 #pragma unroll
     for (int w = 0; w < LV_WAVES; ++w) sacc += red[w][t];
-    a.part_out[(int64_t)(col0 + t) * nb + blockIdx.x] = sacc;
+    a.part_out[(int64_t)phys(col0 + t) * nb + blockIdx.x] = sacc;
   }
 }
 

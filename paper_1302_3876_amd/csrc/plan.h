@@ -43,8 +43,13 @@ struct Plan {
   void* Zw = nullptr;           // FP32 correction (mixed), n x max_nrhs
   double* rho = nullptr;        // FP64 residual (mixed), n x max_nrhs
   double* norms = nullptr;      // [0] ||rho||^2, [1] ||D||^2 (mixed)
-  int32_t* perm = nullptr;      // pivoting: V column of each level (device)
-  std::vector<int32_t> perm_h;  // host copy of perm after a pivoted factorisation
+  // pivoting (plain)
+  bool pivot = false;
+  int32_t* perm = nullptr;      // V/U column used at each level (device)
+  double* gcur = nullptr;       // candidate pivots
+  double* cbuf = nullptr;       // products c_i of the current level
+  int32_t* rem[2] = {nullptr, nullptr};  // remaining columns, alternating
+  int32_t* act[2] = {nullptr, nullptr};  // active lists of the level launches, alternating
 
   Timing timing;
   enkf_sm_info last{};
@@ -66,6 +71,7 @@ struct Plan {
   enkf_status factor_plain();
   enkf_status solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
   enkf_status factor_solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
+  enkf_status sweep_pivot(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
   enkf_status factor_blocked();
   // Z = (R + V V^T)^{-1} D with the blocked factor, all in the working type.
   enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);

@@ -62,7 +62,7 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   stream = s;
   es = dtype_size(d.dtype);
   max_nrhs = d.max_nrhs > 0 ? d.max_nrhs : d.n_ens;
-  if (d.flags & ENKF_FLAG_PIVOT) return fail(ENKF_ERR_NOT_SUPPORTED, "init: pivoting is not available yet");
+  pivot = (d.flags & ENKF_FLAG_PIVOT) != 0;
   const int64_t n = d.n_obs;
   const int N = d.n_ens;
   const int mcols = std::max(N, max_nrhs);
@@ -102,10 +102,18 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   // right factor of an nn product, converted: inner dimension <= N, columns <= mcols
   const size_t oBt = take(nn_bt_bytes(N, mcols));
   size_t oP0 = 0, oP1 = 0, oMinv = 0, oPbuf = 0, oQbuf = 0, oVw = 0, oZw = 0, oRho = 0, oNorm = 0;
+  size_t oGc = 0, oCb = 0, oPerm = 0, oRem = 0, oAct = 0;
   if (!blocked) {
     const size_t part_elems = (size_t)level_row_blocks(d.dtype, 1, n) * (N + max_nrhs);
     oP0 = take(sizeof(double) * part_elems);
     oP1 = take(sizeof(double) * part_elems);
+    if (pivot) {
+      oGc = take(sizeof(double) * N);
+      oCb = take(sizeof(double) * N);
+      oPerm = take(sizeof(int32_t) * N);
+      oRem = take(sizeof(int32_t) * 2 * (size_t)N);
+      oAct = take(sizeof(int32_t) * 2 * (size_t)(N + max_nrhs));
+    }
   } else {
     oMinv = take(sizeof(double) * (size_t)npanel * block * block);
     oPbuf = take(sizeof(double) * (size_t)block * (N + mcols));
@@ -132,6 +140,15 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   if (!blocked) {
     part[0] = reinterpret_cast<double*>(ws + oP0);
     part[1] = reinterpret_cast<double*>(ws + oP1);
+    if (pivot) {
+      gcur = reinterpret_cast<double*>(ws + oGc);
+      cbuf = reinterpret_cast<double*>(ws + oCb);
+      perm = reinterpret_cast<int32_t*>(ws + oPerm);
+      rem[0] = reinterpret_cast<int32_t*>(ws + oRem);
+      rem[1] = rem[0] + N;
+      act[0] = reinterpret_cast<int32_t*>(ws + oAct);
+      act[1] = act[0] + N + max_nrhs;
+    }
   } else {
     Minv = reinterpret_cast<double*>(ws + oMinv);
     Pbuf = reinterpret_cast<double*>(ws + oPbuf);
@@ -157,6 +174,7 @@ enkf_status Plan::factor() { return desc.algo == ENKF_SM_PLAIN ? factor_plain() 
 
 // ------------------------------------------------------------------ plain
 enkf_status Plan::factor_plain() {
+  if (pivot) return sweep_pivot(0, nullptr, 0, nullptr, 0);
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
   const int w = level_vw(desc.dtype);
@@ -226,6 +244,11 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
   a.lds = ldd;
   a.r = r;
   a.vnext = vcol(0);
+  if (pivot) {
+    a.vnext = V;
+    a.vn_idx = perm;
+    a.ldv_idx = ldv;
+  }
   a.part_out = part[0];
   {
     double by, fl;
@@ -248,6 +271,16 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
     b.prev_m = nrhs;
     b.prev_off = 0;
     b.vnext = (k + 1 < N) ? vcol(k + 1) : nullptr;
+    if (pivot) {
+      b.uk = U;
+      b.uk_idx = perm + k;
+      b.ldu_idx = ldu;
+      if (k + 1 < N) {
+        b.vnext = V;
+        b.vn_idx = perm + k + 1;
+        b.ldv_idx = ldv;
+      }
+    }
     b.part_out = part[(k + 1) & 1];
     double by, fl;
     sweep_model(n, nrhs, es, false, b.vnext != nullptr, &by, &fl);
@@ -267,6 +300,7 @@ enkf_status Plan::factor_solve_plain(int nrhs, const void* D, int64_t ldd, void*
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
   if (nrhs == 0) return factor_plain();
+  if (pivot) return sweep_pivot(nrhs, D, ldd, Z, ldz);
   const int w = level_vw(desc.dtype);
   const int vw = (n % w == 0 && vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es) && vec_ok(D, ldd, w, es) &&
                   vec_ok(Z, ldz, w, es)) ? w : 1;
@@ -317,6 +351,113 @@ enkf_status Plan::factor_solve_plain(int nrhs, const void* D, int64_t ldd, void*
     enkf_status st = launch_level(desc.dtype, b, stream);
     if (st != ENKF_SUCCESS) return st;
   }
+  return ENKF_SUCCESS;
+}
+
+// Plain sweeps with the pivoting of Section 3.4 (factorisation, and the Z
+// columns too when nrhs > 0). U keeps V's column order (column j of U holds
+// u_j); perm[k] is the column used at level k and every level's active list
+// is built on the device by the pivot kernel, which also forms gamma_k, so
+// the host never waits. Z lives in the columns after U during the loop and
+// is copied to the caller's buffer at the end.
+enkf_status Plan::sweep_pivot(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz) {
+  const int64_t n = desc.n_obs;
+  const int N = desc.n_ens;
+  const int w = level_vw(desc.dtype);
+  bool ok = n % w == 0 && vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es);
+  if (nrhs > 0) ok = ok && vec_ok(D, ldd, w, es) && vec_ok(Z, ldz, w, es);
+  const int vw = ok ? w : 1;
+  const int nb = level_row_blocks(desc.dtype, vw, n);
+  char* Ub = static_cast<char*>(U);
+  void* Zb = Ub + (size_t)N * ldu * es;
+  enkf_status st;
+  {
+    // candidates 1 + v_i^T R^{-1} v_i and the first pivot
+    TimedLaunch tl(&timing, stream, KC_STEP1, (double)N * n * es + 8.0 * n, 3.0 * (double)N * n);
+    st = launch_diag_partials(desc.dtype, n, N, V, ldv, r, nb, part[1], stream);
+    if (st != ENKF_SUCCESS) return st;
+    PivotArgs pa{};
+    pa.init = 1;
+    pa.N = N;
+    pa.part = part[1];
+    pa.nb = nb;
+    pa.perm = perm;
+    pa.gcur = gcur;
+    pa.rem_out = rem[0];
+    pa.status = status;
+    st = launch_pivot(pa, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  for (int half = 0; half < (nrhs > 0 ? 2 : 1); ++half) {
+    LevelArgs a{};
+    a.n = n;
+    a.vw = vw;
+    a.status = status;
+    a.X = half == 0 ? U : Zb;
+    a.ldx = ldu;
+    a.m = half == 0 ? N : nrhs;
+    a.src = half == 0 ? V : D;
+    a.lds = half == 0 ? ldv : ldd;
+    a.r = r;
+    a.vnext = V;
+    a.vn_idx = perm;
+    a.ldv_idx = ldv;
+    a.part_out = part[0] + (half == 0 ? 0 : (size_t)N * nb);
+    double by, fl;
+    sweep_model(n, a.m, es, true, true, &by, &fl);
+    TimedLaunch tl(&timing, stream, KC_STEP1, by, fl);
+    st = launch_level(desc.dtype, a, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  const int cls = nrhs > 0 ? KC_FUSED_SWEEP : KC_INIT_SWEEP;
+  for (int k = 0; k < N; ++k) {
+    const int m = N - k - 1 + nrhs;
+    double by, fl;
+    sweep_model(n, m, es, false, k + 1 < N, &by, &fl);
+    TimedLaunch tl(&timing, stream, cls, by, fl);
+    PivotArgs pa{};
+    pa.k = k;
+    pa.N = N;
+    pa.nz = nrhs;
+    pa.part = part[k & 1];
+    pa.nb = nb;
+    pa.perm = perm;
+    pa.gamma = gamma;
+    pa.gcur = gcur;
+    pa.cbuf = cbuf;
+    pa.rem_in = rem[k & 1];
+    pa.rem_out = rem[(k + 1) & 1];
+    pa.act_out = act[k & 1];
+    pa.status = status;
+    st = launch_pivot(pa, stream);
+    if (st != ENKF_SUCCESS) return st;
+    if (m == 0) continue;
+    LevelArgs b{};
+    b.n = n;
+    b.vw = vw;
+    b.status = status;
+    b.X = U;
+    b.ldx = ldu;
+    b.m = m;
+    b.colmap = act[k & 1];
+    b.uk = U;
+    b.uk_idx = perm + k;
+    b.ldu_idx = ldu;
+    b.gamma_in = gamma + k;
+    b.prev = part[k & 1];
+    b.prev_m = N - k + nrhs;
+    if (k + 1 < N) {
+      b.vnext = V;
+      b.vn_idx = perm + k + 1;
+      b.ldv_idx = ldv;
+    }
+    b.part_out = part[(k + 1) & 1];
+    st = launch_level(desc.dtype, b, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  if (nrhs > 0)
+    ENKF_HIP_CHECK(hipMemcpy2DAsync(Z, (size_t)ldz * es, Zb, (size_t)ldu * es, (size_t)n * es, nrhs,
+                                    hipMemcpyDeviceToDevice, stream));
   return ENKF_SUCCESS;
 }
 
@@ -602,8 +743,11 @@ enkf_status Plan::get_info(enkf_sm_info* info) {
 enkf_status Plan::get_pivots(double* gamma_host, int32_t* perm_host) {
   ENKF_HIP_CHECK(hipStreamSynchronize(stream));
   ENKF_HIP_CHECK(hipMemcpy(gamma_host, gamma, sizeof(double) * desc.n_ens, hipMemcpyDeviceToHost));
-  if (perm_host)
-    for (int k = 0; k < desc.n_ens; ++k) perm_host[k] = perm_h.empty() ? k : perm_h[k];
+  if (perm_host) {
+    if (pivot) ENKF_HIP_CHECK(hipMemcpy(perm_host, perm, sizeof(int32_t) * desc.n_ens, hipMemcpyDeviceToHost));
+    else
+      for (int k = 0; k < desc.n_ens; ++k) perm_host[k] = k;
+  }
   return ENKF_SUCCESS;
 }
 
