@@ -52,8 +52,10 @@ def _load():
     lib.oracle_build_vd.argtypes = [i64, i32, vp, i64, vp, i64, vp, vp, i64, vp, i64, vp, i64]
     lib.oracle_analysis.argtypes = [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp, i64]
     lib.oracle_local_analysis.argtypes = [i64, i32, vp, vp, i64, vp, i64, i64, vp, i64, i64, vp, vp, vp, vp, i64]
+    lib.oracle_localized_analysis.argtypes = [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.c_double, i64,
+                                              i64, vp, i64]
     for f in ("oracle_sm_solve", "oracle_sm_apply", "oracle_residual", "oracle_build_vd",
-              "oracle_analysis", "oracle_local_analysis"):
+              "oracle_analysis", "oracle_local_analysis", "oracle_localized_analysis"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -145,6 +147,22 @@ def analysis(XB, V, Z):
     XA = np.zeros_like(XB, order="F")
     code = _load().oracle_analysis(n_state, N, n, _p(XB), n_state, _p(V), n, _p(Z), n, _p(XA), n_state)
     _check(code, "oracle_analysis")
+    return XA
+
+
+def localized_analysis(XB, V, Z, loc, length, radius=-1, ring=0):
+    """Partial localization (Section 3.1.2, eq. localized-correction-component):
+    X^A = X^B + (Delta o (S V^T)) Z with delta(i, j) = exp(-d(i, loc_j)/length),
+    zero past `radius` (radius < 0: none), d taken on a ring of `ring` points
+    (ring = 0: no wrap)."""
+    XB, V, Z = _f64(XB), _f64(V), _f64(Z)
+    lc = np.ascontiguousarray(loc, dtype=np.int64)
+    n_state, N = XB.shape
+    n = V.shape[0]
+    XA = np.zeros_like(XB, order="F")
+    code = _load().oracle_localized_analysis(n_state, N, n, _p(XB), n_state, _p(V), n, _p(Z), n, _p(lc),
+                                             ctypes.c_double(float(length)), int(radius), int(ring), _p(XA), n_state)
+    _check(code, "oracle_localized_analysis")
     return XA
 
 

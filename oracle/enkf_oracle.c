@@ -269,6 +269,65 @@ int oracle_analysis(int64_t n_state, int32_t N, int64_t n_obs, const double* XB,
 }
 
 /*
+ * Partial localization (Section 3.1.2, eq. localized-correction-component):
+ *   XA[i, l] = XB[i, l] + sum_k S[i, k] sum_j delta(i, j) V[j, k] Z[j, l],
+ *   S = (XB - mean_row(XB)) / sqrt(N - 1),
+ * with the impact factor of observation j (located at state index loc[j]) on
+ * state point i
+ *   d = |i - loc[j]|, on a ring of `ring` points d = min(d, ring - d);
+ *   delta(i, j) = exp(-d / length), or 0 when radius >= 0 and d > radius
+ * (the paper's Lorenz-96 experiments: ring = length = n_state, no radius).
+ * Written in the formula's order: for each (i, l), the outer sum over k of
+ * S[i, k] times the inner sum over j. O(n_state N^2 n_obs) work.
+ */
+static double impact(int64_t i, int64_t loc, double length, int64_t radius, int64_t ring) {
+    int64_t d = i > loc ? i - loc : loc - i;
+    if (ring > 0 && ring - d < d) d = ring - d;
+    if (radius >= 0 && d > radius) return 0.0;
+    return exp(-(double)d / length);
+}
+
+int oracle_localized_analysis(int64_t n_state, int32_t N, int64_t n_obs, const double* XB, int64_t ldx,
+                              const double* V, int64_t ldv, const double* Z, int64_t ldz, const int64_t* loc,
+                              double length, int64_t radius, int64_t ring, double* XA, int64_t ldxa) {
+    if (n_state < 1 || N < 2 || n_obs < 1 || !(length > 0.0)) return E_ARG;
+    for (int64_t j = 0; j < n_obs; ++j)
+        if (loc[j] < 0 || loc[j] >= n_state) return E_ARG;
+    const double scale = sqrt((double)(N - 1));
+    int fail = 0;
+    #pragma omp parallel
+    {
+        double* S = (double*)malloc(sizeof(double) * (size_t)N);
+        double* dl = (double*)malloc(sizeof(double) * (size_t)n_obs);
+        if (!S || !dl) {
+            #pragma omp atomic write
+            fail = 1;
+        }
+        #pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < n_state; ++i) {
+            if (!S || !dl) continue;
+            double sum = 0.0;
+            for (int32_t k = 0; k < N; ++k) sum += AT(XB, ldx, i, k);
+            const double mean = sum / (double)N;
+            for (int32_t k = 0; k < N; ++k) S[k] = (AT(XB, ldx, i, k) - mean) / scale;
+            for (int64_t j = 0; j < n_obs; ++j) dl[j] = impact(i, loc[j], length, radius, ring);
+            for (int32_t l = 0; l < N; ++l) {
+                double outer = 0.0;
+                for (int32_t k = 0; k < N; ++k) {
+                    double inner = 0.0;
+                    for (int64_t j = 0; j < n_obs; ++j) inner += dl[j] * AT(V, ldv, j, k) * AT(Z, ldz, j, l);
+                    outer += S[k] * inner;
+                }
+                AT(XA, ldxa, i, l) = AT(XB, ldx, i, l) + outer;
+            }
+        }
+        free(S);
+        free(dl);
+    }
+    return fail ? E_NOMEM : OK;
+}
+
+/*
  * Localized analyses, one independent small problem each. Problem p uses the
  * observations win_start[p], win_start[p]+1, ..., win_start[p]+win_len[p]-1,
  * taken modulo n_glob (a cyclic domain), i.e. the rows of the global r, V, D;
