@@ -174,6 +174,27 @@ enkf_status enkf_analysis(enkf_sm_plan plan, int64_t n_state, const void* XB, in
                           int64_t ldz, void* XA, int64_t ldxa);
 
 /*
+ * Partially localized analysis update (Section 3.1.2, eq.
+ * localized-correction-component):
+ *   X^A[i, l] = X^B[i, l] + sum_k S[i, k] sum_j delta(i, j) V[j, k] Z[j, l],
+ * S as in enkf_analysis, with the impact factor of observation j on state
+ * point i
+ *   d = |i - obs_loc[j]|, and on a ring (ring > 0) d = min(d, ring - d);
+ *   delta(i, j) = exp(-d / length), and 0 when radius >= 0 and d > radius.
+ * (The paper's Lorenz-96 runs: ring = length = n_state, no radius.)
+ * obs_loc: DEVICE array of n_obs int64 state indices in [0, n_state) (other
+ * values only change the distances). length finite and > 0; ring 0 or >=
+ * n_state. Other arguments and errors as enkf_analysis; uses the plan's V
+ * and dtype. The n_state x n_obs weighted matrix is never stored: one fused
+ * kernel forms its tiles on the matrix cores and applies them to Z.
+ * 4 n_state n_obs N flops (S V^T recomputed per 128 columns of X^A when N >
+ * 128). Allocates nothing.
+ */
+enkf_status enkf_localized_analysis(enkf_sm_plan plan, int64_t n_state, const void* XB, int64_t ldx, const void* Z,
+                                    int64_t ldz, const int64_t* obs_loc, double length, int64_t radius, int64_t ring,
+                                    void* XA, int64_t ldxa);
+
+/*
  * The same analysis update with the ensemble in its own storage type and the
  * n_state x N x N product on a chosen matrix-core input type: x_dtype is the
  * type of XB and XA; math is ENKF_MATH_F64 (x_dtype F64) or ENKF_MATH_F32,
@@ -204,7 +225,7 @@ enkf_status enkf_sm_get_pivots(enkf_sm_plan plan, double* gamma_host, int32_t* p
  * 2 build, 3 analysis update, 4 split-K products, 5 panel updates (blocked),
  * 6 panel factorisations (blocked), 7 FP64 residuals (refinement),
  * 8 Step 1 (with the plain form's first look-ahead products), 9 level sweeps
- * of a fused factorisation + solve (plain).
+ * of a fused factorisation + solve (plain), 10 localized analysis updates.
  */
 enkf_status enkf_sm_set_timing(enkf_sm_plan plan, int32_t enable);
 enkf_status enkf_sm_get_timing(enkf_sm_plan plan, int32_t kernel_class, double* total_ms, int64_t* launches,

@@ -54,8 +54,10 @@ def _load():
     lib.oracle_local_analysis.argtypes = [i64, i32, vp, vp, i64, vp, i64, i64, vp, i64, i64, vp, vp, vp, vp, i64]
     lib.oracle_localized_analysis.argtypes = [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.c_double, i64,
                                               i64, vp, i64]
+    lib.oracle_localized_rows.argtypes = [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.c_double, i64, i64,
+                                          i64, i64, vp, i64]
     for f in ("oracle_sm_solve", "oracle_sm_apply", "oracle_residual", "oracle_build_vd",
-              "oracle_analysis", "oracle_local_analysis", "oracle_localized_analysis"):
+              "oracle_analysis", "oracle_local_analysis", "oracle_localized_analysis", "oracle_localized_rows"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -164,6 +166,21 @@ def localized_analysis(XB, V, Z, loc, length, radius=-1, ring=0):
                                              ctypes.c_double(float(length)), int(radius), int(ring), _p(XA), n_state)
     _check(code, "oracle_localized_analysis")
     return XA
+
+
+def localized_rows(XB, V, Z, loc, length, radius, ring, row_begin, row_end):
+    """Rows [row_begin, row_end) of localized_analysis (the rows are
+    independent); returns those rows only."""
+    XB, V, Z = _f64(XB), _f64(V), _f64(Z)
+    lc = np.ascontiguousarray(loc, dtype=np.int64)
+    n_state, N = XB.shape
+    n = V.shape[0]
+    XA = np.zeros_like(XB, order="F")
+    code = _load().oracle_localized_rows(n_state, N, n, _p(XB), n_state, _p(V), n, _p(Z), n, _p(lc),
+                                         ctypes.c_double(float(length)), int(radius), int(ring), int(row_begin),
+                                         int(row_end), _p(XA), n_state)
+    _check(code, "oracle_localized_rows")
+    return XA[row_begin:row_end]
 
 
 def local_analysis(r, V, D, XB, win_start, win_len, state_idx):

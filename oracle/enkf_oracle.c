@@ -279,6 +279,8 @@ int oracle_analysis(int64_t n_state, int32_t N, int64_t n_obs, const double* XB,
  * (the paper's Lorenz-96 experiments: ring = length = n_state, no radius).
  * Written in the formula's order: for each (i, l), the outer sum over k of
  * S[i, k] times the inner sum over j. O(n_state N^2 n_obs) work.
+ * oracle_localized_rows computes the rows [row_begin, row_end) only (the
+ * rows are independent); the others of XA are not written.
  */
 static double impact(int64_t i, int64_t loc, double length, int64_t radius, int64_t ring) {
     int64_t d = i > loc ? i - loc : loc - i;
@@ -287,10 +289,12 @@ static double impact(int64_t i, int64_t loc, double length, int64_t radius, int6
     return exp(-(double)d / length);
 }
 
-int oracle_localized_analysis(int64_t n_state, int32_t N, int64_t n_obs, const double* XB, int64_t ldx,
-                              const double* V, int64_t ldv, const double* Z, int64_t ldz, const int64_t* loc,
-                              double length, int64_t radius, int64_t ring, double* XA, int64_t ldxa) {
+int oracle_localized_rows(int64_t n_state, int32_t N, int64_t n_obs, const double* XB, int64_t ldx,
+                          const double* V, int64_t ldv, const double* Z, int64_t ldz, const int64_t* loc,
+                          double length, int64_t radius, int64_t ring, int64_t row_begin, int64_t row_end,
+                          double* XA, int64_t ldxa) {
     if (n_state < 1 || N < 2 || n_obs < 1 || !(length > 0.0)) return E_ARG;
+    if (row_begin < 0 || row_end > n_state || row_begin > row_end) return E_ARG;
     for (int64_t j = 0; j < n_obs; ++j)
         if (loc[j] < 0 || loc[j] >= n_state) return E_ARG;
     const double scale = sqrt((double)(N - 1));
@@ -304,7 +308,7 @@ int oracle_localized_analysis(int64_t n_state, int32_t N, int64_t n_obs, const d
             fail = 1;
         }
         #pragma omp for schedule(dynamic, 4)
-        for (int64_t i = 0; i < n_state; ++i) {
+        for (int64_t i = row_begin; i < row_end; ++i) {
             if (!S || !dl) continue;
             double sum = 0.0;
             for (int32_t k = 0; k < N; ++k) sum += AT(XB, ldx, i, k);
@@ -325,6 +329,14 @@ int oracle_localized_analysis(int64_t n_state, int32_t N, int64_t n_obs, const d
         free(dl);
     }
     return fail ? E_NOMEM : OK;
+}
+
+/* Every row of the partially localized update. */
+int oracle_localized_analysis(int64_t n_state, int32_t N, int64_t n_obs, const double* XB, int64_t ldx,
+                              const double* V, int64_t ldv, const double* Z, int64_t ldz, const int64_t* loc,
+                              double length, int64_t radius, int64_t ring, double* XA, int64_t ldxa) {
+    return oracle_localized_rows(n_state, N, n_obs, XB, ldx, V, ldv, Z, ldz, loc, length, radius, ring, 0, n_state,
+                                 XA, ldxa);
 }
 
 /*

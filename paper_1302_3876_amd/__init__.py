@@ -30,7 +30,7 @@ STATUS = {0: "ENKF_SUCCESS", 1: "ENKF_ERR_INVALID_ARG", 2: "ENKF_ERR_NOT_SPD", 3
           4: "ENKF_ERR_HIP", 5: "ENKF_ERR_OUT_OF_MEMORY", 6: "ENKF_ERR_NOT_SUPPORTED"}
 KERNEL_CLASSES = {"factor_sweep": 0, "solve_sweep": 1, "build": 2, "analysis": 3, "gram": 4,
                   "panel_update": 5, "panel_factor": 6, "residual": 7, "step1": 8,
-                  "fused_sweep": 9}
+                  "fused_sweep": 9, "localize": 10}
 
 
 class EnkfError(RuntimeError):
@@ -81,6 +81,7 @@ def lib():
     L.enkf_sm_factor_solve.argtypes = [vp, vp, vp, i64, i32, vp, i64, vp, i64, ctypes.POINTER(SmInfo)]
     L.enkf_analysis.argtypes = [vp, i64, vp, i64, vp, i64, vp, i64]
     L.enkf_analysis_ex.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, vp, i64]
+    L.enkf_localized_analysis.argtypes = [vp, i64, vp, i64, vp, i64, vp, ctypes.c_double, i64, i64, vp, i64]
     L.enkf_sm_get_info.argtypes = [vp, ctypes.POINTER(SmInfo)]
     L.enkf_sm_get_pivots.argtypes = [vp, vp, vp]
     L.enkf_sm_set_timing.argtypes = [vp, i32]
@@ -98,7 +99,7 @@ def lib():
     L.enkf_last_error_message.argtypes = []
     L.enkf_last_error_message.restype = ctypes.c_char_p
     for name in ("enkf_sm_validate_desc", "enkf_build_vd", "enkf_sm_init", "enkf_sm_refactor", "enkf_sm_factor_solve", "enkf_sm_solve", "enkf_analysis",
-                 "enkf_analysis_ex", "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_set_timing", "enkf_sm_get_timing",
+                 "enkf_analysis_ex", "enkf_localized_analysis", "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_set_timing", "enkf_sm_get_timing",
                  "enkf_local_init", "enkf_local_analysis", "enkf_local_sync"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -283,6 +284,23 @@ class Plan:
         pXA, ldxa = _mat(XA, "XA", xdt)
         _check(lib().enkf_analysis_ex(self._handle, XB.shape[0], xdt, MATH[math], pXB, ldx, pZ, ldz, pXA, ldxa),
                "enkf_analysis_ex")
+        return XA
+
+    def localized_analysis(self, XB, Z, obs_loc, length: float, radius: int = -1, ring: int = 0, XA=None):
+        """X^A = X^B + (Delta o (S V^T)) Z with the impact factors
+        exp(-d/length) (enkf_localized_analysis); obs_loc: int64 device
+        tensor of the observations' state indices."""
+        torch = _torch()
+        pXB, ldx = _mat(XB, "XB", self.dtype)
+        pZ, ldz = _mat(Z, "Z", self.dtype)
+        if XA is None:
+            XA = colmajor(XB.shape[0], XB.shape[1], XB.dtype, XB.device)
+        pXA, ldxa = _mat(XA, "XA", self.dtype)
+        pl = _vec(obs_loc, "obs_loc", torch.int64)
+        if obs_loc.shape[0] != self.n_obs:
+            raise ValueError("localized_analysis: obs_loc needs one entry per observation")
+        _check(lib().enkf_localized_analysis(self._handle, XB.shape[0], pXB, ldx, pZ, ldz, pl, float(length),
+                                             int(radius), int(ring), pXA, ldxa), "enkf_localized_analysis")
         return XA
 
     def info(self):

@@ -29,7 +29,8 @@ enum KernelClass : int {
   KC_RESIDUAL = 7,     // FP64 residual of the refinement
   KC_STEP1 = 8,        // Step 1 (R^{-1} V, R^{-1} D) and the plain form's first products
   KC_FUSED_SWEEP = 9,  // plain: U- and Z-updates of one level in one launch (factor + solve)
-  KC_COUNT = 10
+  KC_LOCALIZE = 10,    // partially localized analysis update
+  KC_COUNT = 11
 };
 
 void set_error(const std::string& msg);
@@ -125,6 +126,21 @@ struct PivotArgs {
 enkf_status launch_diag_partials(enkf_dtype dt, int64_t n, int N, const void* V, int64_t ldv, const double* r,
                                  int nb, double* part, hipStream_t s);
 enkf_status launch_pivot(const PivotArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- partial localization
+struct LocalizeArgs {
+  int64_t n_state, n_obs;
+  int N;
+  const void* XB; int64_t ldx;
+  const void* V; int64_t ldv;
+  const void* Z; int64_t ldz;
+  const int64_t* loc;        // state index of each observation (device)
+  double length;             // e-folding distance (> 0)
+  int64_t radius;            // impact is zero past this distance; < 0: no cut-off
+  int64_t ring;              // distances on a ring of this many points; 0: no wrap
+  void* XA; int64_t ldxa;
+};
+enkf_status launch_localize(enkf_dtype dt, const LocalizeArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- build
 enkf_status launch_build_vd(enkf_dtype dt, int64_t n_state, int n_ens, const void* XB, int64_t ldx,

@@ -234,6 +234,41 @@ enkf_status enkf_analysis(enkf_sm_plan plan, int64_t n_state, const void* XB, in
   return p->analysis(n_state, p->desc.dtype, math, XB, ldx, Z, ldz, XA, ldxa);
 }
 
+enkf_status enkf_localized_analysis(enkf_sm_plan plan, int64_t n_state, const void* XB, int64_t ldx, const void* Z,
+                                    int64_t ldz, const int64_t* obs_loc, double length, int64_t radius, int64_t ring,
+                                    void* XA, int64_t ldxa) {
+  if (!plan) return fail(ENKF_ERR_INVALID_ARG, "localized analysis: plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  enkf_status st = analysis_checks(p, n_state, p->desc.dtype, XB, ldx, Z, ldz, XA, ldxa);
+  if (st != ENKF_SUCCESS) return st;
+  if (!obs_loc) return fail(ENKF_ERR_INVALID_ARG, "localized analysis: obs_loc is NULL");
+  if (!(length > 0.0) || !std::isfinite(length))
+    return fail(ENKF_ERR_INVALID_ARG, "localized analysis: length must be finite and > 0");
+  if (ring != 0 && ring < n_state) return fail(ENKF_ERR_INVALID_ARG, "localized analysis: ring must be 0 or >= n_state");
+  LocalizeArgs a{};
+  a.n_state = n_state;
+  a.n_obs = p->desc.n_obs;
+  a.N = p->desc.n_ens;
+  a.XB = XB;
+  a.ldx = ldx;
+  a.V = p->V;
+  a.ldv = p->ldv;
+  a.Z = Z;
+  a.ldz = ldz;
+  a.loc = obs_loc;
+  a.length = length;
+  a.radius = radius;
+  a.ring = ring;
+  a.XA = XA;
+  a.ldxa = ldxa;
+  const double N = p->desc.n_ens, ns = (double)n_state, no = (double)p->desc.n_obs;
+  const double chunks = std::ceil(N / 128.0);
+  TimedLaunch tl(&p->timing, p->stream, KC_LOCALIZE, 2.0 * ns * N * p->es + 2.0 * no * N * p->es,
+                 4.0 * ns * no * N);
+  (void)chunks;
+  return launch_localize(p->desc.dtype, a, p->stream);
+}
+
 enkf_status enkf_analysis_ex(enkf_sm_plan plan, int64_t n_state, enkf_dtype x_dtype, enkf_math math, const void* XB,
                              int64_t ldx, const void* Z, int64_t ldz, void* XA, int64_t ldxa) {
   if (!plan) return fail(ENKF_ERR_INVALID_ARG, "analysis: plan is NULL");

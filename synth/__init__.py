@@ -212,6 +212,12 @@ def c5(seed: Optional[int] = None, n_state: int = 2_097_152, n_ens: int = 1024) 
     return lorenz_workload("c5", n_state, n_ens, 4, SEED_BASE + 5 if seed is None else seed)
 
 
+def c6(seed: Optional[int] = None, n_state: int = 32_768, n_ens: int = 64) -> Workload:
+    """Partial localization workload: Lorenz-96 ring n_state=32,768, N=64,
+    every 2nd variable observed (n_obs=16,384), r ~ U(0.005,0.02)."""
+    return lorenz_workload("c6", n_state, n_ens, 2, SEED_BASE + 6 if seed is None else seed)
+
+
 def small_vd(n_obs: int, n_ens: int, seed: int, r_range=(0.5, 2.0), v_scale: float = 1.0,
              nrhs: Optional[int] = None):
     """Small random (r, V, D) for checks: V ~ v_scale N(0,1)/sqrt(N), D ~ N(0,1)."""

@@ -1,0 +1,93 @@
+"""Partial localization (Section 3.1.2) on the fused HIP kernel against the
+FP64 oracle's formula, through the C ABI.
+
+Tolerances: the correction sums N products over the state members and n_obs
+weighted products over the observations; in FP64 the difference from the
+oracle's order is a few units of roundoff of the absolute sums, so it is
+bounded by 1e-12 times the largest |correction| (plus the X^B scale for the
+addition). FP32 storage and FP32 matrix cores: 2e-5 of the same scale."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _pk():
+    import paper_1302_3876_amd as pk
+    return pk
+
+
+def _inputs(n_state, N, stride, seed):
+    """Lorenz-96-shaped ensemble on a ring, every `stride`-th point observed,
+    V from the anomalies, Z from an FP64 solve of the same system."""
+    g = np.random.default_rng(seed)
+    XB = 2.3 + 3.6 * g.standard_normal((n_state, N))
+    loc = np.arange(0, n_state, stride, dtype=np.int64)
+    n_obs = loc.shape[0]
+    A = (XB - XB.mean(axis=1, keepdims=True)) / np.sqrt(N - 1)
+    V = A[loc]
+    r = g.uniform(0.5, 1.5, n_obs)
+    D = g.standard_normal((n_obs, N))
+    Z = oracle.sm_solve(r, V, D)["Z"]
+    return XB, V, Z, loc, r
+
+
+def _gate(XA, ref, XB, tol):
+    corr = np.max(np.abs(ref - XB))
+    err = np.max(np.abs(XA - ref))
+    assert err <= tol * (corr + 1e-3 * np.max(np.abs(XB))), (err, corr)
+
+
+@pytest.mark.parametrize("n_state,N,stride,length,radius,ring", [
+    (512, 40, 2, 512.0, -1, 512),      # the paper's Lorenz-96 form: ring, length = n_state
+    (100, 160, 3, 7.5, 10, 0),         # N > 128 (two column chunks), radius, no ring, ragged tiles
+    (2048, 64, 2, 64.0, -1, 2048),
+    (33, 2, 1, 3.0, 4, 33),
+])
+def test_localized_fp64_matches_oracle(n_state, N, stride, length, radius, ring):
+    import torch
+    print(f"localize fp64 n_state={n_state} N={N} stride={stride}", flush=True)
+    pk = _pk()
+    XB, V, Z, loc, r = _inputs(n_state, N, stride, seed=n_state + N)
+    plan = pk.Plan(dev(r), dev(V))
+    XA = plan.localized_analysis(dev(XB), dev(Z), dev(loc), length, radius, ring)
+    torch.cuda.synchronize()
+    ref = oracle.localized_analysis(XB, V, Z, loc, length, radius, ring)
+    _gate(host(XA), ref, XB, 1e-12)
+
+
+def test_localized_without_taper_is_the_analysis():
+    import torch
+    pk = _pk()
+    XB, V, Z, loc, r = _inputs(300, 24, 2, seed=9)
+    plan = pk.Plan(dev(r), dev(V))
+    XA = host(plan.localized_analysis(dev(XB), dev(Z), dev(loc), 1e300))
+    torch.cuda.synchronize()
+    _gate(XA, oracle.analysis(XB, V, Z), XB, 1e-12)
+
+
+def test_localized_fp32():
+    import torch
+    pk = _pk()
+    XB, V, Z, loc, r = _inputs(1024, 48, 2, seed=5)
+    f = lambda a: a.astype(np.float32).astype(np.float64)
+    plan = pk.Plan(dev(r), dev(V, torch.float32))
+    XA = plan.localized_analysis(dev(XB, torch.float32), dev(Z, torch.float32), dev(loc), 1024.0, -1, 1024)
+    torch.cuda.synchronize()
+    ref = oracle.localized_analysis(f(XB), f(V), f(Z), loc, 1024.0, -1, 1024)
+    _gate(host(XA), ref, f(XB), 2e-5)
+
+
+def test_localized_bad_arguments():
+    import torch
+    pk = _pk()
+    XB, V, Z, loc, r = _inputs(64, 8, 2, seed=1)
+    plan = pk.Plan(dev(r), dev(V))
+    for kw in ({"length": 0.0}, {"length": float("inf")}, {"length": 1.0, "ring": 10}):
+        with pytest.raises(pk.EnkfError) as e:
+            plan.localized_analysis(dev(XB), dev(Z), dev(loc), **kw)
+        assert e.value.code == 1

@@ -67,6 +67,13 @@ def test_cyclic_shift_permutes_rows():
     assert np.allclose(np.roll(XA, s, axis=0), XA2, rtol=1e-12, atol=1e-13)
 
 
+def test_row_range_matches_full():
+    XB, V, Z, loc = _case(n_state=50)
+    full = oracle.localized_analysis(XB, V, Z, loc, 6.0, 12, 50)
+    part = oracle.localized_rows(XB, V, Z, loc, 6.0, 12, 50, 17, 31)
+    assert np.array_equal(part, full[17:31])
+
+
 def test_exact_rational_brute_force():
     # radius 0 keeps only the observations at the same index, where
     # delta = exp(0) = 1, so every sum is an exact rational.
