@@ -54,10 +54,12 @@ def _load():
     lib.oracle_local_analysis.argtypes = [i64, i32, vp, vp, i64, vp, i64, i64, vp, i64, i64, vp, vp, vp, vp, i64]
     lib.oracle_localized_analysis.argtypes = [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.c_double, i64,
                                               i64, vp, i64]
+    lib.oracle_sm_solve_block_r.argtypes = [i64, i32, i64, vp, vp, vp, i64, vp, i64, i32, vp, i64, vp]
     lib.oracle_localized_rows.argtypes = [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.c_double, i64, i64,
                                           i64, i64, vp, i64]
     for f in ("oracle_sm_solve", "oracle_sm_apply", "oracle_residual", "oracle_build_vd",
-              "oracle_analysis", "oracle_local_analysis", "oracle_localized_analysis", "oracle_localized_rows"):
+              "oracle_analysis", "oracle_local_analysis", "oracle_localized_analysis", "oracle_localized_rows",
+              "oracle_sm_solve_block_r"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -100,6 +102,31 @@ def sm_solve(r, V, D, pivot: bool = False, want_factor: bool = False):
                                    1 if pivot else 0, _p(perm), ctypes.byref(ops))
     _check(code, "oracle_sm_solve")
     return {"Z": Z, "gamma": gamma, "perm": perm, "longops": int(ops.value), "U": U}
+
+
+def pack_blocks(blocks):
+    """Offsets (nblk + 1) and the column-major blocks packed one after the
+    other, the layout of a block-diagonal R used by the solvers."""
+    sizes = [b.shape[0] for b in blocks]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    packed = np.concatenate([np.asarray(b, dtype=np.float64).ravel(order="F") for b in blocks])
+    return off, packed
+
+
+def sm_solve_block_r(blocks, V, D):
+    """Iterative Sherman-Morrison solve with a block-diagonal R = diag(blocks)
+    (Section 2.1; Step 1 block by block, Section 3.1). Returns Z and gamma."""
+    off, packed = pack_blocks(blocks)
+    V, D = _f64(V), _f64(D)
+    n, N = V.shape
+    nrhs = D.shape[1]
+    assert off[-1] == n
+    Z = np.zeros((n, nrhs), dtype=np.float64, order="F")
+    gamma = np.zeros(N, dtype=np.float64)
+    code = _load().oracle_sm_solve_block_r(n, N, len(blocks), _p(off), _p(packed), _p(V), n, _p(D), n, nrhs,
+                                           _p(Z), n, _p(gamma))
+    _check(code, "oracle_sm_solve_block_r")
+    return {"Z": Z, "gamma": gamma}
 
 
 def sm_apply(r, V, U, gamma, X, perm=None):

@@ -63,13 +63,85 @@ static double dot_col(int64_t n, const double* a, const double* b) {
  * longops  optional: multiplications and divisions performed, the count of
  *          Section 3.2 (3(N^2 n + N n) for nrhs = N without pivoting).
  */
+/*
+ * Step 1 for a block-diagonal R (Section 2.1: R = diag(R_1, ..., R_B), each
+ * R_b an SPD N_b x N_b block; Section 3.1: Z0 = R^{-1} D, U0 = R^{-1} V are
+ * formed block by block): Y = R^{-1} X with a dense Cholesky factorisation
+ * R_b = L L^T of each block, then L y = x and L^T z = y per column.
+ * Block b covers rows off[b] .. off[b+1]-1; its matrix is column-major at
+ * Rb + sum_{c<b} N_c^2.
+ */
+static int block_r_solve(int64_t nblk, const int64_t* off, const double* Rb, const double* X, int64_t ldx,
+                         int32_t m, double* Y, int64_t ldy) {
+    int64_t roff = 0;
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t r0 = off[b], s = off[b + 1] - off[b];
+        double* L = (double*)malloc(sizeof(double) * (size_t)(s * s));
+        double* y = (double*)malloc(sizeof(double) * (size_t)s);
+        if (!L || !y) { free(L); free(y); return E_NOMEM; }
+        memcpy(L, Rb + roff, sizeof(double) * (size_t)(s * s));
+        for (int64_t j = 0; j < s; ++j) {          /* column-oriented Cholesky */
+            double d = L[j + j * s];
+            for (int64_t k = 0; k < j; ++k) d -= L[j + k * s] * L[j + k * s];
+            if (!(d > 0.0) || !isfinite(d)) { free(L); free(y); return E_NOT_SPD; }
+            d = sqrt(d);
+            L[j + j * s] = d;
+            for (int64_t i = j + 1; i < s; ++i) {
+                double v = L[i + j * s];
+                for (int64_t k = 0; k < j; ++k) v -= L[i + k * s] * L[j + k * s];
+                L[i + j * s] = v / d;
+            }
+        }
+        for (int32_t c = 0; c < m; ++c) {
+            for (int64_t i = 0; i < s; ++i) {      /* L y = x */
+                double v = AT(X, ldx, r0 + i, c);
+                for (int64_t k = 0; k < i; ++k) v -= L[i + k * s] * y[k];
+                y[i] = v / L[i + i * s];
+            }
+            for (int64_t i = s - 1; i >= 0; --i) { /* L^T z = y */
+                double v = y[i];
+                for (int64_t k = i + 1; k < s; ++k) v -= L[k + i * s] * AT(Y, ldy, r0 + k, c);
+                AT(Y, ldy, r0 + i, c) = v / L[i + i * s];
+            }
+        }
+        free(L);
+        free(y);
+        roff += s * s;
+    }
+    return OK;
+}
+
+static int sm_solve_core(int64_t n, int32_t N, const double* r, int64_t nblk, const int64_t* boff,
+                         const double* Rb, const double* V, int64_t ldv, const double* D, int64_t ldd, int32_t nrhs,
+                         double* Z, int64_t ldz, double* Ufac, double* gamma, int32_t pivot, int32_t* perm,
+                         int64_t* longops);
+
 int oracle_sm_solve(int64_t n, int32_t N, const double* r, const double* V, int64_t ldv,
                     const double* D, int64_t ldd, int32_t nrhs, double* Z, int64_t ldz,
                     double* Ufac, double* gamma, int32_t pivot, int32_t* perm, int64_t* longops) {
+    if (!r) return E_ARG;
+    return sm_solve_core(n, N, r, 0, NULL, NULL, V, ldv, D, ldd, nrhs, Z, ldz, Ufac, gamma, pivot, perm, longops);
+}
+
+/* The same solve with a block-diagonal R (Step 1 by block_r_solve). */
+int oracle_sm_solve_block_r(int64_t n, int32_t N, int64_t nblk, const int64_t* boff, const double* Rb,
+                            const double* V, int64_t ldv, const double* D, int64_t ldd, int32_t nrhs, double* Z,
+                            int64_t ldz, double* gamma) {
+    if (nblk < 1 || !boff || !Rb || boff[0] != 0 || boff[nblk] != n) return E_ARG;
+    for (int64_t b = 0; b < nblk; ++b)
+        if (boff[b + 1] <= boff[b]) return E_ARG;
+    return sm_solve_core(n, N, NULL, nblk, boff, Rb, V, ldv, D, ldd, nrhs, Z, ldz, NULL, gamma, 0, NULL, NULL);
+}
+
+static int sm_solve_core(int64_t n, int32_t N, const double* r, int64_t nblk, const int64_t* boff,
+                         const double* Rb, const double* V, int64_t ldv, const double* D, int64_t ldd, int32_t nrhs,
+                         double* Z, int64_t ldz, double* Ufac, double* gamma, int32_t pivot, int32_t* perm,
+                         int64_t* longops) {
     if (n < 1 || N < 1 || nrhs < 0 || ldv < n || (nrhs > 0 && (ldd < n || ldz < n))) return E_ARG;
-    if (!r || !V || (nrhs > 0 && (!D || !Z))) return E_ARG;
-    for (int64_t i = 0; i < n; ++i)
-        if (!(r[i] > 0.0) || !isfinite(r[i])) return E_NOT_SPD;
+    if (!V || (nrhs > 0 && (!D || !Z))) return E_ARG;
+    if (r)
+        for (int64_t i = 0; i < n; ++i)
+            if (!(r[i] > 0.0) || !isfinite(r[i])) return E_NOT_SPD;
 
     double* U = (double*)malloc(sizeof(double) * (size_t)n * (size_t)N);
     double* Vw = (double*)malloc(sizeof(double) * (size_t)n * (size_t)N);
@@ -85,13 +157,19 @@ int oracle_sm_solve(int64_t n, int32_t N, const double* r, const double* V, int6
     }
 
     /* Step 1. */
-    #pragma omp parallel for schedule(static)
-    for (int32_t j = 0; j < N; ++j)
-        for (int64_t i = 0; i < n; ++i) AT(U, n, i, j) = AT(Vw, n, i, j) / r[i];
-    #pragma omp parallel for schedule(static)
-    for (int32_t j = 0; j < nrhs; ++j)
-        for (int64_t i = 0; i < n; ++i) AT(Z, ldz, i, j) = AT(D, ldd, i, j) / r[i];
-    ops += n * (int64_t)N + n * (int64_t)nrhs;
+    if (r) {
+        #pragma omp parallel for schedule(static)
+        for (int32_t j = 0; j < N; ++j)
+            for (int64_t i = 0; i < n; ++i) AT(U, n, i, j) = AT(Vw, n, i, j) / r[i];
+        #pragma omp parallel for schedule(static)
+        for (int32_t j = 0; j < nrhs; ++j)
+            for (int64_t i = 0; i < n; ++i) AT(Z, ldz, i, j) = AT(D, ldd, i, j) / r[i];
+        ops += n * (int64_t)N + n * (int64_t)nrhs;
+    } else {
+        int st = block_r_solve(nblk, boff, Rb, Vw, n, N, U, n);
+        if (st == OK && nrhs > 0) st = block_r_solve(nblk, boff, Rb, D, ldd, nrhs, Z, ldz);
+        if (st != OK) { free(U); free(Vw); free(h); free(pm); return st; }
+    }
 
     int status = OK;
     for (int32_t k = 0; k < N; ++k) {
