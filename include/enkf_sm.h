@@ -140,6 +140,41 @@ enkf_status enkf_sm_init(enkf_sm_plan* out, const enkf_sm_desc* desc, const doub
 enkf_status enkf_sm_refactor(enkf_sm_plan plan, const double* r, const void* V, int64_t ldv);
 
 /*
+ * Block-diagonal observation error covariance (Section 2.1: R =
+ * diag(R_1, ..., R_B), each R_b SPD of size N_b, sum N_b = n_obs). Step 1
+ * (eq. SM-step-1) then applies R^{-1} block by block (Section 3.1; at most
+ * O(n N^2) work, Section 3.2) and the level sweeps are unchanged.
+ *   offsets: HOST array of n_blocks + 1 row offsets, offsets[0] = 0 <
+ *            offsets[1] < ... < offsets[n_blocks] = n_obs, every block of at
+ *            most ENKF_MAX_R_BLOCK rows;
+ *   blocks:  DEVICE, FP64; block b (rows offsets[b] .. offsets[b+1]-1) is a
+ *            dense column-major N_b x N_b matrix stored at
+ *            blocks + sum_{c<b} N_c^2. Read at init / refactor only.
+ */
+#define ENKF_MAX_R_BLOCK 64
+
+typedef struct {
+    int64_t n_blocks;
+    const int64_t* offsets;
+    const double* blocks;
+} enkf_block_r;
+
+/*
+ * enkf_sm_init with a block-diagonal R. The blocks are factored R_b = L L^T
+ * in FP64 on the device (a block that is not SPD latches ENKF_ERR_NOT_SPD),
+ * then V as in enkf_sm_init. Plain and blocked algorithms in FP64 or FP32
+ * storage; pivoting and the mixed-precision refinement need a diagonal R
+ * (ENKF_ERR_NOT_SUPPORTED). Such a plan is refactored with
+ * enkf_sm_refactor_block_r (enkf_sm_refactor and enkf_sm_factor_solve return
+ * ENKF_ERR_INVALID_ARG) and solved with enkf_sm_solve. Allocates.
+ */
+enkf_status enkf_sm_init_block_r(enkf_sm_plan* out, const enkf_sm_desc* desc, const enkf_block_r* R, const void* V,
+                                 int64_t ldv, void* stream);
+
+/* New block values (same structure) and V: refactor without allocation. */
+enkf_status enkf_sm_refactor_block_r(enkf_sm_plan plan, const double* R_blocks, const void* V, int64_t ldv);
+
+/*
  * The D-dependent half of S*: Step 1 for D (Z0 = R^{-1} D) and the Z-updates
  * of every level (eq. SM-step-2-Z): Z = (R + V V^T)^{-1} D.
  * D and Z are n_obs x nrhs (nrhs >= 0; the analysis has nrhs = N) in the

@@ -78,6 +78,8 @@ def lib():
     L.enkf_sm_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SmDesc), vp, vp, i64, vp]
     L.enkf_sm_solve.argtypes = [vp, i32, vp, i64, vp, i64, ctypes.POINTER(SmInfo)]
     L.enkf_sm_refactor.argtypes = [vp, vp, vp, i64]
+    L.enkf_sm_init_block_r.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SmDesc), ctypes.POINTER(BlockR), vp, i64, vp]
+    L.enkf_sm_refactor_block_r.argtypes = [vp, vp, vp, i64]
     L.enkf_sm_factor_solve.argtypes = [vp, vp, vp, i64, i32, vp, i64, vp, i64, ctypes.POINTER(SmInfo)]
     L.enkf_analysis.argtypes = [vp, i64, vp, i64, vp, i64, vp, i64]
     L.enkf_analysis_ex.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, vp, i64]
@@ -98,7 +100,8 @@ def lib():
     L.enkf_status_string.restype = ctypes.c_char_p
     L.enkf_last_error_message.argtypes = []
     L.enkf_last_error_message.restype = ctypes.c_char_p
-    for name in ("enkf_sm_validate_desc", "enkf_build_vd", "enkf_sm_init", "enkf_sm_refactor", "enkf_sm_factor_solve", "enkf_sm_solve", "enkf_analysis",
+    for name in ("enkf_sm_validate_desc", "enkf_build_vd", "enkf_sm_init", "enkf_sm_init_block_r", "enkf_sm_refactor",
+                 "enkf_sm_refactor_block_r", "enkf_sm_factor_solve", "enkf_sm_solve", "enkf_analysis",
                  "enkf_analysis_ex", "enkf_localized_analysis", "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_set_timing", "enkf_sm_get_timing",
                  "enkf_local_init", "enkf_local_analysis", "enkf_local_sync"):
         getattr(L, name).restype = ctypes.c_int
@@ -207,11 +210,19 @@ def enkf_build_vd(XB, obs_idx, y, E, V=None, D=None):
     return V, D
 
 
+class BlockR(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int64), ("offsets", ctypes.c_void_p), ("blocks", ctypes.c_void_p)]
+
+
 class Plan:
-    """enkf_sm_init / enkf_sm_solve / enkf_analysis on one (r, V)."""
+    """enkf_sm_init / enkf_sm_solve / enkf_analysis on one (r, V).
+
+    With ``block_r=(offsets, blocks)`` (numpy int64 host offsets, FP64 device
+    tensor of the packed column-major blocks) R is block diagonal and r is
+    ignored (enkf_sm_init_block_r)."""
 
     def __init__(self, r, V, algo: str = "plain", math: Optional[str] = None, block: int = 0, max_nrhs: int = 0,
-                 refine_max_iter: int = 0, refine_tol: float = 0.0, pivot: bool = False):
+                 refine_max_iter: int = 0, refine_tol: float = 0.0, pivot: bool = False, block_r=None):
         torch = _torch()
         self.dtype = _dtype_code(V)
         if math is None:
@@ -223,8 +234,27 @@ class Plan:
         self._r, self._V = r, V  # borrowed by the plan until close()
         self._handle = ctypes.c_void_p()
         self.n_obs, self.n_ens = n, N
+        if block_r is not None:
+            import numpy as np
+            off = np.ascontiguousarray(block_r[0], dtype=np.int64)
+            blocks = block_r[1]
+            pb = _vec(blocks, "blocks", torch.float64)
+            self._block_r = (off, blocks)
+            R = BlockR(len(off) - 1, ctypes.c_void_p(off.ctypes.data), pb)
+            _check(lib().enkf_sm_init_block_r(ctypes.byref(self._handle), ctypes.byref(self.desc), ctypes.byref(R),
+                                              pV, ldv, _stream()), "enkf_sm_init_block_r")
+            return
         _check(lib().enkf_sm_init(ctypes.byref(self._handle), ctypes.byref(self.desc),
                                   _vec(r, "r", torch.float64), pV, ldv, _stream()), "enkf_sm_init")
+
+    def refactor_block_r(self, blocks, V):
+        """New block values (same structure) and V (enkf_sm_refactor_block_r)."""
+        torch = _torch()
+        pV, ldv = _mat(V, "V", self.dtype)
+        _check(lib().enkf_sm_refactor_block_r(self._handle, _vec(blocks, "blocks", torch.float64), pV, ldv),
+               "enkf_sm_refactor_block_r")
+        self._block_r = (self._block_r[0], blocks)
+        self._V = V
 
     def refactor(self, r, V):
         """New (r, V) of the same shape: recompute the factor in the same

@@ -127,6 +127,16 @@ enkf_status launch_diag_partials(enkf_dtype dt, int64_t n, int N, const void* V,
                                  int nb, double* part, hipStream_t s);
 enkf_status launch_pivot(const PivotArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------- block-diagonal R
+constexpr int kMaxRBlock = ENKF_MAX_R_BLOCK;
+// R_b = L L^T for every block (off: row offsets, poff: packed offsets, both
+// nblk + 1, device); Y = R^{-1} X block by block (FP64 arithmetic).
+enkf_status launch_block_chol(int64_t nblk, const int64_t* off, const int64_t* poff, const double* Rb, double* Lf,
+                              unsigned* status, hipStream_t s);
+enkf_status launch_block_solve(enkf_dtype dt, int max_bs, int64_t nblk, int m, const int64_t* off,
+                               const int64_t* poff, const double* Lf, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                               hipStream_t s);
+
 // ---------------------------------------------------------------- partial localization
 struct LocalizeArgs {
   int64_t n_state, n_obs;

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
     if constexpr (STEP1) {
 #pragma unroll
       for (int e = 0; e < VW; ++e) {
-        const double rv = a.r[rowc[r] + e];
+        const double rv = a.r ? a.r[rowc[r] + e] : 1.0;   // no r: Step 1 already applied (block R)
         if (ok && (!(rv > 0.0) || !__builtin_isfinite(rv))) atomicOr(a.status, kStatusNotSpd);
         hrow[r][e] = ok ? 1.0 / rv : 0.0;
       }

@@ -51,6 +51,16 @@ struct Plan {
   int32_t* rem[2] = {nullptr, nullptr};  // remaining columns, alternating
   int32_t* act[2] = {nullptr, nullptr};  // active lists of the level launches, alternating
 
+  // block-diagonal R (r == nullptr): row offsets, packed offsets and the
+  // Cholesky factors of the blocks, in a second allocation
+  bool block_r = false;
+  int64_t nblk = 0;
+  int max_bs = 0;
+  char* bws = nullptr;
+  int64_t* boff = nullptr;
+  int64_t* bpoff = nullptr;
+  double* Lf = nullptr;
+
   Timing timing;
   enkf_sm_info last{};
 
@@ -62,6 +72,8 @@ struct Plan {
   enkf_status analysis(int64_t n_state, enkf_dtype x_dtype, enkf_math math, const void* XB, int64_t ldx,
                        const void* Z, int64_t ldz, void* XA, int64_t ldxa);
   enkf_status get_info(enkf_sm_info* info);
+  enkf_status set_block_r(int64_t nblk, const int64_t* off_host);
+  enkf_status factor_block_r(const double* Rblocks);
   enkf_status get_pivots(double* gamma_host, int32_t* perm_host);
   enkf_status read_status(unsigned* st);
   enkf_status clear_status();
@@ -72,6 +84,7 @@ struct Plan {
   enkf_status solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
   enkf_status factor_solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
   enkf_status sweep_pivot(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
+  enkf_status block_step1(enkf_dtype dt, int m, const void* X, int64_t ldx, void* Y, int64_t ldy);
   enkf_status factor_blocked();
   // Z = (R + V V^T)^{-1} D with the blocked factor, all in the working type.
   enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);

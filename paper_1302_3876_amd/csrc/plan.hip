@@ -166,8 +166,47 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
 }
 
 Plan::~Plan() {
-  if (stream || ws) (void)hipStreamSynchronize(stream);
+  if (stream || ws || bws) (void)hipStreamSynchronize(stream);
   if (ws) (void)hipFree(ws);
+  if (bws) (void)hipFree(bws);
+}
+
+// Block-diagonal R: keep the block structure on the device and factor the
+// blocks (Section 2.1). Offsets are validated by the caller.
+enkf_status Plan::set_block_r(int64_t nb_, const int64_t* off_host) {
+  block_r = true;
+  nblk = nb_;
+  max_bs = 0;
+  std::vector<int64_t> poff_h(nblk + 1, 0);
+  for (int64_t b = 0; b < nblk; ++b) {
+    const int64_t sz = off_host[b + 1] - off_host[b];
+    max_bs = std::max<int>(max_bs, (int)sz);
+    poff_h[b + 1] = poff_h[b] + sz * sz;
+  }
+  const size_t bytes = sizeof(int64_t) * 2 * (size_t)(nblk + 1) + sizeof(double) * (size_t)poff_h[nblk];
+  hipError_t e = hipMalloc(&bws, bytes);
+  if (e != hipSuccess) {
+    bws = nullptr;
+    return fail(ENKF_ERR_OUT_OF_MEMORY, "init: block R workspace");
+  }
+  boff = reinterpret_cast<int64_t*>(bws);
+  bpoff = boff + nblk + 1;
+  Lf = reinterpret_cast<double*>(bpoff + nblk + 1);
+  ENKF_HIP_CHECK(hipMemcpyAsync(boff, off_host, sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, stream));
+  ENKF_HIP_CHECK(hipMemcpyAsync(bpoff, poff_h.data(), sizeof(int64_t) * (nblk + 1), hipMemcpyHostToDevice, stream));
+  ENKF_HIP_CHECK(hipStreamSynchronize(stream));   // poff_h leaves scope
+  return ENKF_SUCCESS;
+}
+
+enkf_status Plan::factor_block_r(const double* Rblocks) {
+  return launch_block_chol(nblk, boff, bpoff, Rblocks, Lf, status, stream);
+}
+
+// Step 1 of a block-R plan: Y = R^{-1} X in the working type.
+enkf_status Plan::block_step1(enkf_dtype dt, int m, const void* X, int64_t ldx, void* Y, int64_t ldy) {
+  TimedLaunch tl(&timing, stream, KC_STEP1, 2.0 * (double)desc.n_obs * m * dtype_size(dt),
+                 2.0 * (double)desc.n_obs * m * max_bs);
+  return launch_block_solve(dt, max_bs, nblk, m, boff, bpoff, Lf, X, ldx, Y, ldy, stream);
 }
 
 enkf_status Plan::factor() { return desc.algo == ENKF_SM_PLAIN ? factor_plain() : factor_blocked(); }
@@ -180,7 +219,12 @@ enkf_status Plan::factor_plain() {
   const int w = level_vw(desc.dtype);
   const int vw = (n % w == 0 && vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es)) ? w : 1;
   const int nb = level_row_blocks(desc.dtype, vw, n);
-  // Step 1 for V: U0 = R^{-1} V and the products v_1^T u_j^{(0)}.
+  // Step 1 for V: U0 = R^{-1} V and the products v_1^T u_j^{(0)} (block R:
+  // the block solves first, then the same pass with no scaling).
+  if (block_r) {
+    enkf_status st = block_step1(desc.dtype, N, V, ldv, U, ldu);
+    if (st != ENKF_SUCCESS) return st;
+  }
   LevelArgs a{};
   a.n = n;
   a.vw = vw;
@@ -188,8 +232,8 @@ enkf_status Plan::factor_plain() {
   a.X = U;
   a.ldx = ldu;
   a.m = N;
-  a.src = V;
-  a.lds = ldv;
+  a.src = block_r ? U : V;
+  a.lds = block_r ? ldu : ldv;
   a.r = r;
   a.vnext = vcol(0);
   a.part_out = part[0];
@@ -233,6 +277,10 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
   const int w = level_vw(desc.dtype);
   const int vw = (n % w == 0 && vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es) && vec_ok(D, ldd, w, es) &&
                   vec_ok(Z, ldz, w, es)) ? w : 1;
+  if (block_r) {
+    enkf_status st = block_step1(desc.dtype, nrhs, D, ldd, Z, ldz);
+    if (st != ENKF_SUCCESS) return st;
+  }
   LevelArgs a{};
   a.n = n;
   a.vw = vw;
@@ -240,8 +288,8 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
   a.X = Z;
   a.ldx = ldz;
   a.m = nrhs;
-  a.src = D;
-  a.lds = ldd;
+  a.src = block_r ? Z : D;
+  a.lds = block_r ? ldz : ldd;
   a.r = r;
   a.vnext = vcol(0);
   if (pivot) {
@@ -301,6 +349,10 @@ enkf_status Plan::factor_solve_plain(int nrhs, const void* D, int64_t ldd, void*
   const int N = desc.n_ens;
   if (nrhs == 0) return factor_plain();
   if (pivot) return sweep_pivot(nrhs, D, ldd, Z, ldz);
+  if (block_r) {
+    enkf_status st = factor_plain();
+    return st != ENKF_SUCCESS ? st : solve_plain(nrhs, D, ldd, Z, ldz);
+  }
   const int w = level_vw(desc.dtype);
   const int vw = (n % w == 0 && vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es) && vec_ok(D, ldd, w, es) &&
                   vec_ok(Z, ldz, w, es)) ? w : 1;
@@ -490,8 +542,12 @@ enkf_status Plan::factor_blocked() {
   const void* Vk = vwork();
   const int64_t ldvk = ldvw();
   {
-    TimedLaunch tl(&timing, stream, KC_STEP1, 2.0 * n * N * wes + 8.0 * n, (double)n * N);
-    st = launch_scale_rows(wdt, n, N, Vk, ldvk, r, U, ldu, status, stream);
+    if (block_r) {
+      st = block_step1(wdt, N, Vk, ldvk, U, ldu);
+    } else {
+      TimedLaunch tl(&timing, stream, KC_STEP1, 2.0 * n * N * wes + 8.0 * n, (double)n * N);
+      st = launch_scale_rows(wdt, n, N, Vk, ldvk, r, U, ldu, status, stream);
+    }
     if (st != ENKF_SUCCESS) return st;
   }
   for (int p = 0; p < npanel; ++p) {
@@ -544,7 +600,8 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
   if (nrhs == 0) return ENKF_SUCCESS;
   {
     TimedLaunch tl(&timing, stream, KC_STEP1, 2.0 * n * nrhs * wes + 8.0 * n, (double)n * nrhs);
-    st = launch_scale_rows(wdt, n, nrhs, D, ldd, r, Z, ldz, status, stream);
+    st = block_r ? launch_block_solve(wdt, max_bs, nblk, nrhs, boff, bpoff, Lf, D, ldd, Z, ldz, stream)
+                 : launch_scale_rows(wdt, n, nrhs, D, ldd, r, Z, ldz, status, stream);
     if (st != ENKF_SUCCESS) return st;
   }
   const void* Vk = vwork();

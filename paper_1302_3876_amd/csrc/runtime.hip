@@ -163,10 +163,56 @@ enkf_status enkf_sm_init(enkf_sm_plan* out, const enkf_sm_desc* desc, const doub
   return ENKF_SUCCESS;
 }
 
+enkf_status enkf_sm_init_block_r(enkf_sm_plan* out, const enkf_sm_desc* desc, const enkf_block_r* R, const void* V,
+                                 int64_t ldv, void* stream) {
+  if (!out) return fail(ENKF_ERR_INVALID_ARG, "init_block_r: out is NULL");
+  *out = nullptr;
+  enkf_status st = validate_desc(desc);
+  if (st != ENKF_SUCCESS) return st;
+  if (!R || !R->offsets || !R->blocks || !V) return fail(ENKF_ERR_INVALID_ARG, "init_block_r: NULL argument");
+  if (ldv < desc->n_obs) return fail(ENKF_ERR_INVALID_ARG, "init_block_r: ldv < n_obs");
+  if (R->n_blocks < 1 || R->offsets[0] != 0 || R->offsets[R->n_blocks] != desc->n_obs)
+    return fail(ENKF_ERR_INVALID_ARG, "init_block_r: offsets must run from 0 to n_obs");
+  for (int64_t b = 0; b < R->n_blocks; ++b) {
+    const int64_t sz = R->offsets[b + 1] - R->offsets[b];
+    if (sz < 1) return fail(ENKF_ERR_INVALID_ARG, "init_block_r: offsets must increase");
+    if (sz > ENKF_MAX_R_BLOCK) return fail(ENKF_ERR_NOT_SUPPORTED, "init_block_r: block larger than ENKF_MAX_R_BLOCK");
+  }
+  if (desc->flags & ENKF_FLAG_PIVOT) return fail(ENKF_ERR_NOT_SUPPORTED, "init_block_r: pivoting needs a diagonal R");
+  if (desc->algo == ENKF_SM_BLOCKED && desc->math != (desc->dtype == ENKF_F64 ? ENKF_MATH_F64 : ENKF_MATH_F32))
+    return fail(ENKF_ERR_NOT_SUPPORTED, "init_block_r: the refinement residual needs a diagonal R");
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return fail(ENKF_ERR_OUT_OF_MEMORY, "init: plan");
+  st = p->create(*desc, nullptr, V, ldv, static_cast<hipStream_t>(stream));
+  if (st == ENKF_SUCCESS) st = p->set_block_r(R->n_blocks, R->offsets);
+  if (st == ENKF_SUCCESS) st = p->factor_block_r(R->blocks);
+  if (st == ENKF_SUCCESS) st = p->factor();
+  if (st != ENKF_SUCCESS) {
+    delete p;
+    return st;
+  }
+  *out = reinterpret_cast<enkf_sm_plan>(p);
+  return ENKF_SUCCESS;
+}
+
+enkf_status enkf_sm_refactor_block_r(enkf_sm_plan plan, const double* R_blocks, const void* V, int64_t ldv) {
+  if (!plan) return fail(ENKF_ERR_INVALID_ARG, "refactor_block_r: plan is NULL");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p->block_r) return fail(ENKF_ERR_INVALID_ARG, "refactor_block_r: the plan has a diagonal R");
+  if (!R_blocks || !V) return fail(ENKF_ERR_INVALID_ARG, "refactor_block_r: NULL argument");
+  if (ldv < p->desc.n_obs) return fail(ENKF_ERR_INVALID_ARG, "refactor_block_r: ldv < n_obs");
+  p->V = V;
+  p->ldv = ldv;
+  enkf_status st = p->clear_status();
+  if (st == ENKF_SUCCESS) st = p->factor_block_r(R_blocks);
+  return st == ENKF_SUCCESS ? p->factor() : st;
+}
+
 enkf_status enkf_sm_refactor(enkf_sm_plan plan, const double* r, const void* V, int64_t ldv) {
   if (!plan) return fail(ENKF_ERR_INVALID_ARG, "refactor: plan is NULL");
   if (!r || !V) return fail(ENKF_ERR_INVALID_ARG, "refactor: r or V is NULL");
   Plan* p = reinterpret_cast<Plan*>(plan);
+  if (p->block_r) return fail(ENKF_ERR_INVALID_ARG, "refactor: the plan has a block-diagonal R (enkf_sm_refactor_block_r)");
   if (ldv < p->desc.n_obs) return fail(ENKF_ERR_INVALID_ARG, "refactor: ldv < n_obs");
   p->r = r;
   p->V = V;
@@ -194,6 +240,7 @@ enkf_status enkf_sm_factor_solve(enkf_sm_plan plan, const double* r, const void*
   if (!plan) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: plan is NULL");
   if (!r || !V) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: r or V is NULL");
   Plan* p = reinterpret_cast<Plan*>(plan);
+  if (p->block_r) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: the plan has a block-diagonal R");
   if (ldv < p->desc.n_obs) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: ldv < n_obs");
   if (nrhs < 0 || nrhs > p->max_nrhs) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: nrhs outside [0, max_nrhs]");
   if (nrhs > 0) {

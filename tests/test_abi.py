@@ -28,12 +28,14 @@ def test_struct_layout_matches_c_compiler(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "enkf_sm.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(enkf_sm_desc), offsetof(enkf_sm_desc, refine_tol),"
         " offsetof(enkf_sm_desc, flags), sizeof(enkf_sm_info), offsetof(enkf_sm_info, gamma_max),"
-        " offsetof(enkf_sm_info, device_status)); return 0;}\n")
+        " offsetof(enkf_sm_info, device_status)); printf(\"%zu %zu\\n\", sizeof(enkf_block_r),"
+        " offsetof(enkf_block_r, blocks)); return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     want = [ctypes.sizeof(pk.SmDesc), pk.SmDesc.refine_tol.offset, pk.SmDesc.flags.offset,
-            ctypes.sizeof(pk.SmInfo), pk.SmInfo.gamma_max.offset, pk.SmInfo.device_status.offset]
+            ctypes.sizeof(pk.SmInfo), pk.SmInfo.gamma_max.offset, pk.SmInfo.device_status.offset,
+            ctypes.sizeof(pk.BlockR), pk.BlockR.blocks.offset]
     assert [int(x) for x in got] == want
 
 
@@ -76,6 +78,8 @@ def test_null_arguments_rejected_without_gpu():
     assert lib.enkf_sm_init(ctypes.byref(h), ctypes.byref(_desc()), None, None, 100, None) == 1
     assert lib.enkf_sm_solve(None, 1, None, 1, None, 1, None) == 1
     assert lib.enkf_sm_factor_solve(None, None, None, 1, 1, None, 1, None, 1, None) == 1
+    assert lib.enkf_sm_init_block_r(ctypes.byref(h), ctypes.byref(_desc()), None, None, 100, None) == 1
+    assert lib.enkf_sm_refactor_block_r(None, None, None, 100) == 1
     assert lib.enkf_analysis(None, 1, None, 1, None, 1, None, 1) == 1
     assert lib.enkf_build_vd(10, 1, 0, None, 10, None, 5, None, None, 5, None, None, 5, None) == 1
     assert lib.enkf_build_vd(10, 4, 0, None, 10, None, 5, None, None, 5, None, None, 5, None) == 1
