@@ -56,13 +56,14 @@ FORMS = {
     "plain_f64": ("plain", "f64", "f64", 0),
     "plain_f32": ("plain", "f32", "f32", 0),
     "plain_f64_pivot": ("plain", "f64", "f64", 0),
+    "plain_f64_blockr4": ("plain", "f64", "f64", 0),
     "blocked_f64": ("blocked", "f64", "f64", 0),
     "blocked_f32": ("blocked", "f32", "f32", 0),
     "mixed_f32": ("blocked", "f64", "f32", 8),
     "mixed_bf16x3": ("blocked", "f64", "bf16x3", 12),
     "mixed_f16x2": ("blocked", "f64", "f16x2", 12),
 }
-DEFAULT_FORMS = {"c2": ["plain_f64", "plain_f32", "blocked_f64", "mixed_f32", "plain_f64_pivot"],
+DEFAULT_FORMS = {"c2": ["plain_f64", "plain_f32", "blocked_f64", "mixed_f32", "plain_f64_pivot", "plain_f64_blockr4"],
                  "c3": ["blocked_f64", "mixed_f32", "mixed_bf16x3", "mixed_f16x2", "plain_f64"]}
 
 
@@ -99,15 +100,30 @@ def run_form(name, w, args, pk, torch, cache):
     # mixed forms refine until the FP64 residual is <= 1e-10 (synchronous
     # check per refinement step), at most `refine` steps
     tol = 1e-10 if refine else 0.0
+    block_r = None
+    if name.endswith("_blockr4"):
+        # R block diagonal, blocks of 4 neighbouring observations with
+        # correlation 0.5^|i-j| and the diagonal r: R_b = D^(1/2) C D^(1/2)
+        rh = g["r"].cpu().numpy()
+        nb = w.n_obs // 4
+        idx = np.arange(4)
+        C = 0.5 ** np.abs(idx[:, None] - idx[None, :])
+        sd = np.sqrt(rh[: nb * 4].reshape(nb, 4))
+        Rb = sd[:, :, None] * C[None] * sd[:, None, :]
+        packed = np.ascontiguousarray(Rb.transpose(0, 2, 1)).ravel()      # column-major per block
+        block_r = (np.arange(0, w.n_obs + 1, 4, dtype=np.int64), torch.as_tensor(packed).cuda())
     plan = pk.Plan(g["r"], g["V"], algo=algo, math=math, block=block, refine_max_iter=refine, refine_tol=tol,
-                   pivot=name.endswith("_pivot"))
+                   pivot=name.endswith("_pivot"), block_r=block_r)
     last = {}
 
     def step():
         if full:
             pk.enkf_build_vd(g["XB"], g["obs"], g["y"], g["E"], g["V"], g["D"])
         # factorisation + solve in one call (plain: one level loop over U and Z)
-        if refine:
+        if block_r is not None:
+            plan.refactor_block_r(block_r[1], g["V"])
+            plan.solve(g["D"], g["Z"])
+        elif refine:
             _, last["info"] = plan.factor_solve(g["r"], g["V"], g["D"], g["Z"], info=True)
         else:
             plan.factor_solve(g["r"], g["V"], g["D"], g["Z"])
@@ -150,7 +166,11 @@ def run_form(name, w, args, pk, torch, cache):
     Vh = np.asfortranarray(g["V"].cpu().numpy().astype(np.float64))
     Dh = np.asfortranarray(g["D"].cpu().numpy().astype(np.float64))
     Zh = np.asfortranarray(g["Z"].cpu().numpy().astype(np.float64))
-    rho = Dh - w.r[:, None] * Zh - Vh @ (Vh.T @ Zh)
+    if block_r is not None:
+        RZ = np.einsum("bij,bjm->bim", Rb, Zh.reshape(-1, 4, Zh.shape[1])).reshape(Zh.shape)
+        rho = Dh - RZ - Vh @ (Vh.T @ Zh)
+    else:
+        rho = Dh - w.r[:, None] * Zh - Vh @ (Vh.T @ Zh)
     relres = float(np.linalg.norm(rho) / np.linalg.norm(Dh))
     del Vh, Dh, Zh, rho
     out = {"ms_per_step": round(ms, 4), "solves_per_s": round(1000.0 / ms, 3), "algo": algo, "storage": storage,

@@ -55,11 +55,12 @@ def _load():
     lib.oracle_localized_analysis.argtypes = [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.c_double, i64,
                                               i64, vp, i64]
     lib.oracle_sm_solve_block_r.argtypes = [i64, i32, i64, vp, vp, vp, i64, vp, i64, i32, vp, i64, vp]
+    lib.oracle_l96_rk4.argtypes = [i64, i64, vp, i64, i64, ctypes.c_double, ctypes.c_double]
     lib.oracle_localized_rows.argtypes = [i64, i32, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.c_double, i64, i64,
                                           i64, i64, vp, i64]
     for f in ("oracle_sm_solve", "oracle_sm_apply", "oracle_residual", "oracle_build_vd",
               "oracle_analysis", "oracle_local_analysis", "oracle_localized_analysis", "oracle_localized_rows",
-              "oracle_sm_solve_block_r"):
+              "oracle_sm_solve_block_r", "oracle_l96_rk4"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -208,6 +209,41 @@ def localized_rows(XB, V, Z, loc, length, radius, ring, row_begin, row_end):
                                          int(row_end), _p(XA), n_state)
     _check(code, "oracle_localized_rows")
     return XA[row_begin:row_end]
+
+
+def l96_forecast(X, nsteps, F=8.0, dt=0.05):
+    """Lorenz-96 RK4 forecast of every column of X (a copy is returned)."""
+    X = np.array(X, dtype=np.float64, order="F", copy=True)
+    if X.ndim == 1:
+        X = X[:, None]
+    n, m = X.shape
+    _check(_load().oracle_l96_rk4(n, m, _p(X), n, int(nsteps), float(F), float(dt)), "oracle_l96_rk4")
+    return X
+
+
+def cycle_l96(XB0, obs_idx, ys, Es, r, nsteps, F=8.0, dt=0.05, localize=None, truths=None):
+    """The cycling filter of the Lorenz-96 experiments (Section 4): per cycle
+    c, forecast the ensemble nsteps RK4 steps, build V and D from the
+    perturbed observations ys[c] + Es[c] (Section 2), solve with the
+    iterative Sherman-Morrison formula (Section 3.1) and update the ensemble,
+    with the partial localization of Section 3.1.2 when
+    localize = (length, ring). Returns the final ensemble and, with truths,
+    the forecast and analysis RMSE of the ensemble mean per cycle."""
+    XB = np.array(XB0, dtype=np.float64, order="F", copy=True)
+    rmse_f, rmse_a = [], []
+    for c in range(len(ys)):
+        XB = l96_forecast(XB, nsteps, F, dt)
+        V, D = build_vd(XB, obs_idx, ys[c], Es[c])
+        Z = sm_solve(r, V, D)["Z"]
+        if localize is None:
+            XA = analysis(XB, V, Z)
+        else:
+            XA = localized_analysis(XB, V, Z, obs_idx, localize[0], -1, localize[1])
+        if truths is not None:
+            rmse_f.append(float(np.sqrt(np.mean((XB.mean(axis=1) - truths[c]) ** 2))))
+            rmse_a.append(float(np.sqrt(np.mean((XA.mean(axis=1) - truths[c]) ** 2))))
+        XB = XA
+    return XB, rmse_f, rmse_a
 
 
 def local_analysis(r, V, D, XB, win_start, win_len, state_idx):

@@ -478,3 +478,46 @@ int oracle_local_analysis(int64_t n_glob, int32_t N, const double* r, const doub
     }
     return status;
 }
+
+/*
+ * Lorenz-96 forecast (the model of the Lorenz-96 experiments, Section 4):
+ *   dx_i/dt = (x_{i+1} - x_{i-2}) x_{i-1} - x_i + F,  indices cyclic,
+ * advanced by the classical fourth-order Runge-Kutta method with step dt,
+ *   k1 = f(x), k2 = f(x + dt/2 k1), k3 = f(x + dt/2 k2), k4 = f(x + dt k3),
+ *   x <- x + dt/6 (k1 + 2 k2 + 2 k3 + k4),
+ * nsteps times, for each of the m columns of X (n x m, ldx). n >= 4.
+ */
+static void l96_f(int64_t n, const double* x, double F, double* f) {
+    for (int64_t i = 0; i < n; ++i) {
+        const double xp1 = x[(i + 1) % n], xm1 = x[(i + n - 1) % n], xm2 = x[(i + n - 2) % n];
+        f[i] = (xp1 - xm2) * xm1 - x[i] + F;
+    }
+}
+
+int oracle_l96_rk4(int64_t n, int64_t m, double* X, int64_t ldx, int64_t nsteps, double F, double dt) {
+    if (n < 4 || m < 0 || ldx < n || nsteps < 0) return E_ARG;
+    int fail = 0;
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < m; ++j) {
+        double* w = (double*)malloc(sizeof(double) * (size_t)n * 5);
+        if (!w) {
+            #pragma omp atomic write
+            fail = 1;
+            continue;
+        }
+        double *k1 = w, *k2 = w + n, *k3 = w + 2 * n, *k4 = w + 3 * n, *y = w + 4 * n;
+        double* x = X + j * ldx;
+        for (int64_t s = 0; s < nsteps; ++s) {
+            l96_f(n, x, F, k1);
+            for (int64_t i = 0; i < n; ++i) y[i] = x[i] + 0.5 * dt * k1[i];
+            l96_f(n, y, F, k2);
+            for (int64_t i = 0; i < n; ++i) y[i] = x[i] + 0.5 * dt * k2[i];
+            l96_f(n, y, F, k3);
+            for (int64_t i = 0; i < n; ++i) y[i] = x[i] + dt * k3[i];
+            l96_f(n, y, F, k4);
+            for (int64_t i = 0; i < n; ++i) x[i] += dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+        }
+        free(w);
+    }
+    return fail ? E_NOMEM : OK;
+}
