@@ -91,6 +91,8 @@ def lib():
                                      ctypes.POINTER(dbl)]
     L.enkf_sm_destroy.argtypes = [vp]
     L.enkf_sm_destroy.restype = None
+    L.enkf_l96_forecast.argtypes = [i64, i32, vp, i64, i32, dbl, dbl, vp]
+    L.enkf_l96_forecast.restype = ctypes.c_int
     L.enkf_local_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(LocalDesc), vp, vp, vp, vp]
     L.enkf_local_analysis.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, i64, vp]
     L.enkf_local_sync.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -429,3 +431,48 @@ class LocalPlan:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ Lorenz-96 cycling filter
+def l96_forecast(X, nsteps: int, F: float = 8.0, dt: float = 0.05):
+    """Advance every column of the FP64 device matrix X by nsteps RK4 steps of
+    the Lorenz-96 model, in place (enkf_l96_forecast)."""
+    pX, ldx = _mat(X, "X", ENKF_F64)
+    _check(lib().enkf_l96_forecast(X.shape[0], X.shape[1], pX, ldx, int(nsteps), float(F), float(dt), _stream()),
+           "enkf_l96_forecast")
+    return X
+
+
+def cycle_l96(XB, obs_idx, ys, Es, r, nsteps: int, F: float = 8.0, dt: float = 0.05, localize=None,
+              algo: str = "plain", block: int = 0):
+    """The Lorenz-96 cycling filter on the device: per cycle c, forecast the
+    ensemble XB (FP64, n_state x N, updated in place), build V and D from
+    ys[c] and Es[c] (device tensors), factor and solve (enkf_sm_factor_solve)
+    and update the ensemble (enkf_analysis, or enkf_localized_analysis with
+    localize = (length, ring)). Yields after each cycle (forecast mean,
+    analysis mean) as device tensors, so the caller can score them."""
+    torch = _torch()
+    n_state, N = XB.shape
+    n_obs = obs_idx.shape[0]
+    V = colmajor(n_obs, N, torch.float64, XB.device)
+    D = colmajor(n_obs, N, torch.float64, XB.device)
+    Z = colmajor(n_obs, N, torch.float64, XB.device)
+    XA = colmajor(n_state, N, torch.float64, XB.device)
+    plan = None
+    try:
+        for c in range(len(ys)):
+            l96_forecast(XB, nsteps, F, dt)
+            enkf_build_vd(XB, obs_idx, ys[c], Es[c], V, D)
+            if plan is None:
+                plan = Plan(r, V, algo=algo, block=block)
+            plan.factor_solve(r, V, D, Z)
+            if localize is None:
+                plan.analysis(XB, Z, XA)
+            else:
+                plan.localized_analysis(XB, Z, obs_idx, localize[0], -1, localize[1], XA)
+            fmean = XB.mean(dim=1)
+            XB.copy_(XA)
+            yield fmean, XA.mean(dim=1)
+    finally:
+        if plan is not None:
+            plan.close()

@@ -218,6 +218,30 @@ def c6(seed: Optional[int] = None, n_state: int = 32_768, n_ens: int = 64) -> Wo
     return lorenz_workload("c6", n_state, n_ens, 2, SEED_BASE + 6 if seed is None else seed)
 
 
+def l96_cycle_inputs(n_state: int, n_ens: int, cycles: int, nsteps: int, seed: int, sd_obs: float = 0.01,
+                     bg_err: float = 0.05):
+    """Inputs of a Lorenz-96 cycling run in the setting of the paper's
+    Lorenz-96 experiments: H = I (n_obs = n_state), R = sd_obs^2 I, truth spun
+    up 1000 steps from a seeded start, members = truth (1 + bg_err g) with g
+    ~ N(0, 1) (a 5% background error), then per cycle the truth advanced
+    nsteps RK4 steps, y = truth + N(0, R) and perturbations E ~ N(0, R).
+    Returns (XB0, obs_idx, r, truths, ys, Es)."""
+    truth = l96_advance(np.ascontiguousarray(8.0 + normal(seed, P_TRUTH0, n_state)), 1000)
+    g = normal(seed, P_MEMBER, n_state * n_ens).reshape(n_ens, n_state).T
+    XB = np.asfortranarray(truth[:, None] * (1.0 + bg_err * g))
+    obs = np.arange(n_state, dtype=np.int64)
+    r = np.full(n_state, sd_obs ** 2)
+    truths, ys, Es = [], [], []
+    t = truth.copy()
+    for c in range(cycles):
+        t = l96_advance(t, nsteps)
+        truths.append(t.copy())
+        ys.append(t + sd_obs * normal(seed, P_OBS, n_state, offset=c * n_state))
+        e = normal(seed, P_EPERT, n_state * n_ens, offset=c * n_state * n_ens)
+        Es.append(np.asfortranarray(sd_obs * e.reshape(n_ens, n_state).T))
+    return XB, obs, r, truths, ys, Es
+
+
 def small_vd(n_obs: int, n_ens: int, seed: int, r_range=(0.5, 2.0), v_scale: float = 1.0,
              nrhs: Optional[int] = None):
     """Small random (r, V, D) for checks: V ~ v_scale N(0,1)/sqrt(N), D ~ N(0,1)."""
