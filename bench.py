@@ -318,12 +318,12 @@ def run_loc(w, args, pk, torch):
     return out
 
 
-CYCLE = {"n_state": 1000, "n_ens": 400, "cycles": 10, "nsteps": 20, "seed": 20130219}
+CYCLE = {"n_state": 1000, "n_ens": 1000, "cycles": 10, "nsteps": 20, "seed": 20130219}
 
 
 def run_cycle(args, pk, torch):
     """The Lorenz-96 cycling filter in the paper's N ~ n_obs regime: n_state =
-    n_obs = 1000, N = 400, R = 0.01^2 I, one time unit (20 RK4 steps) per
+    n_obs = 1000, N = 1000, R = 0.01^2 I, one time unit (20 RK4 steps) per
     cycle; a step is one cycle (forecast of every member + analysis). Plain
     and blocked solves."""
     import numpy as np
