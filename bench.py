@@ -59,11 +59,13 @@ FORMS = {
     "plain_f64_blockr4": ("plain", "f64", "f64", 0),
     "blocked_f64": ("blocked", "f64", "f64", 0),
     "blocked_f32": ("blocked", "f32", "f32", 0),
+    "blocked_f64_refined": ("blocked", "f64", "f64", 1),
     "mixed_f32": ("blocked", "f64", "f32", 8),
     "mixed_bf16x3": ("blocked", "f64", "bf16x3", 12),
     "mixed_f16x2": ("blocked", "f64", "f16x2", 12),
 }
-DEFAULT_FORMS = {"c2": ["plain_f64", "plain_f32", "blocked_f64", "mixed_f32", "plain_f64_pivot", "plain_f64_blockr4"],
+DEFAULT_FORMS = {"c2": ["plain_f64", "plain_f32", "blocked_f64", "blocked_f64_refined", "mixed_f32", "plain_f64_pivot",
+                        "plain_f64_blockr4"],
                  "c3": ["blocked_f64", "mixed_f32", "mixed_bf16x3", "mixed_f16x2", "plain_f64"]}
 
 
@@ -97,9 +99,10 @@ def run_form(name, w, args, pk, torch, cache):
     if full:
         pk.enkf_build_vd(g["XB"], g["obs"], g["y"], g["E"], g["V"], g["D"])
     block = args.block if algo == "blocked" else 0
-    # mixed forms refine until the FP64 residual is <= 1e-10 (synchronous
-    # check per refinement step), at most `refine` steps
-    tol = 1e-10 if refine else 0.0
+    # mixed forms stop once the FP64 residual is <= 1e-10, checked
+    # synchronously per refinement step, at most `refine` steps; FP64 panels
+    # take exactly `refine` correction steps
+    tol = (0.0 if math == "f64" else 1e-10) if refine else 0.0
     block_r = None
     if name.endswith("_blockr4"):
         # R block diagonal, blocks of 4 neighbouring observations with
@@ -181,7 +184,7 @@ def run_form(name, w, args, pk, torch, cache):
     return out
 
 
-def traffic_record(source_rel: str):
+def traffic_record(source_rel: str, kernel: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary under
     profiles/ (FETCH_SIZE + WRITE_SIZE, calibrated with a copy of known size),
     or None once the kernel source no longer has the hash they were taken at."""
@@ -195,7 +198,7 @@ def traffic_record(source_rel: str):
         for line in open(path):
             if line.startswith("traffic-record:"):
                 rec = json.loads(line.split(":", 1)[1])
-                if rec.get("source") == source_rel and rec.get("source_sha256") == sha:
+                if rec.get("source") == source_rel and rec.get("source_sha256") == sha and rec.get("kernel") == kernel:
                     return rec["bytes_per_launch"]
     return None
 
@@ -203,12 +206,19 @@ def traffic_record(source_rel: str):
 def roofline_of(form, name):
     k = form["kernels"]
     if form["algo"] == "plain":
-        c = k["fused_sweep"]
+        # the dominant class: the Z-sweep (when the U and Z loops run
+        # separately, which the library picks when their joint working set
+        # would overflow the last-level cache) or the fused sweep
+        fused = "fused_sweep" in k
+        c = k["fused_sweep" if fused else "solve_sweep"]
         ach = c["alg_bytes_per_launch"] / (c["avg_launch_us"] * 1e-6) / 1e9
-        traffic = traffic_record("paper_1302_3876_amd/csrc/level_kernels.hip") if name == "plain_f64" else None
+        traffic = traffic_record("paper_1302_3876_amd/csrc/level_kernels.hip",
+                                 "level_kernel<double, 2, false, true, true>" if fused else
+                                 "level_kernel<double, 2, false, true, false>") if name == "plain_f64" else None
+        what = "fused factor + solve sweep" if fused else "solve sweep (Z columns)"
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"level_kernel ({name}: fused factor + solve sweep, one launch per level)",
+                "kernel": f"level_kernel ({name}: {what}, one launch per level)",
                 "avg_launch_us": c["avg_launch_us"], "alg_bytes_per_launch": c["alg_bytes_per_launch"]}
     c = k["gram"]
     ach = c["alg_flops_per_launch"] / (c["avg_launch_us"] * 1e-6) / 1e12

@@ -85,8 +85,10 @@ typedef struct {
     enkf_math math;         /* must be ENKF_MATH_F64 for PLAIN F64, ENKF_MATH_F32 for PLAIN F32 */
     int32_t block;          /* panel width b for BLOCKED (1..N); 0 = pick one */
     int32_t max_nrhs;       /* largest nrhs a solve may pass; 0 = n_ens */
-    int32_t refine_max_iter;/* mixed precision: maximum refinement steps (0 = none) */
-    double refine_tol;      /* mixed precision: stop when ||D - W Z||_F / ||D||_F <= tol */
+    int32_t refine_max_iter;/* blocked: maximum FP64 refinement steps (0 = none). Mixed precision, or
+                               FP64 panels (F64/F64): the Woodbury panel update is not backward
+                               stable, residual corrections restore FP64 accuracy */
+    double refine_tol;      /* refinement: stop when ||D - W Z||_F / ||D||_F <= tol */
     uint32_t flags;         /* ENKF_FLAG_* */
 } enkf_sm_desc;
 

@@ -21,6 +21,8 @@ enkf_status launch_small_gemm(int b, int m, const double* Minv, const double* Pr
 // NULL for no scaling); FP32 -> FP64 copy or accumulation multiplied back.
 enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float* Y, int64_t ldy, const double* sumsq,
                            hipStream_t s);
+// Z += X, FP64.
+enkf_status launch_add(int64_t n, int m, const double* X, int64_t ldx, double* Z, int64_t ldz, hipStream_t s);
 enkf_status launch_widen(int64_t n, int m, const float* W, int64_t ldw, double* Z, int64_t ldz, bool accumulate,
                          const double* sumsq, hipStream_t s);
 // out[0] = ||X||_F^2, out[1] = ||Y||_F^2 (fixed-order two-stage sums).

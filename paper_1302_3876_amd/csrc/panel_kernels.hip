@@ -137,6 +137,14 @@ __global__ __launch_bounds__(256) void widen_kernel(int64_t n, int m, const floa
   }
 }
 
+// Z += X (FP64), the correction of an FP64 refinement step.
+__global__ __launch_bounds__(256) void add_kernel(int64_t n, int m, const double* __restrict__ X, int64_t ldx,
+                                                  double* __restrict__ Z, int64_t ldz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int j = blockIdx.y; j < m; j += gridDim.y) Z[i + (int64_t)j * ldz] += X[i + (int64_t)j * ldx];
+}
+
 constexpr int NORM_BLOCKS = 1024;
 
 // Per-block partial sums of squares of two n x m FP64 matrices, in a fixed
@@ -227,6 +235,14 @@ enkf_status launch_panel_factor(int b, const double* P, int64_t ldp, double* gam
                                 hipStream_t s) {
   if (b < 1 || b > kMaxPanel) return fail(ENKF_ERR_NOT_SUPPORTED, "panel width outside [1, 128]");
   panel_factor_kernel<<<1, 256, 0, s>>>(b, P, ldp, gamma_out, Minv, status);
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
+enkf_status launch_add(int64_t n, int m, const double* X, int64_t ldx, double* Z, int64_t ldz, hipStream_t s) {
+  if (n <= 0 || m <= 0) return ENKF_SUCCESS;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(m < 16 ? m : 16));
+  add_kernel<<<grid, 256, 0, s>>>(n, m, X, ldx, Z, ldz);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }

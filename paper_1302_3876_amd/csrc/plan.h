@@ -38,6 +38,7 @@ struct Plan {
   double* Qbuf = nullptr;       // b x max(N, max_nrhs)
   // mixed precision (math narrower than dtype): FP32 working copies
   bool mixed = false;
+  bool refine64 = false;        // FP64 blocked solve with FP64 refinement
   enkf_dtype wdt = ENKF_F64;    // working storage type of U, panels, Z-sweeps
   void* Vw = nullptr;           // FP32 copy of V (mixed)
   void* Zw = nullptr;           // FP32 correction (mixed), n x max_nrhs
@@ -89,6 +90,8 @@ struct Plan {
   // Z = (R + V V^T)^{-1} D with the blocked factor, all in the working type.
   enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
   enkf_status solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
+  enkf_status solve_refined64(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
+  enkf_status residual64(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz);
   const void* vwork() const { return mixed ? Vw : V; }
   int64_t ldvw() const { return mixed ? ldu : ldv; }
   const void* vcol(int k) const;  // V column used at level k

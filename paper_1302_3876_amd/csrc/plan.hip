@@ -37,6 +37,9 @@ void sweep_model(int64_t n, int m, size_t es, bool step1, bool look, double* by,
 
 }  // namespace
 
+// Last-level (infinity) cache of the MI355X: 256 MiB.
+constexpr double kMallBytes = 256.0 * 1024.0 * 1024.0;
+
 const void* Plan::vcol(int k) const { return static_cast<const char*>(V) + (size_t)k * (size_t)ldv * es; }
 
 // Panel products in the working type; narrow math types round the FP32
@@ -68,6 +71,10 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   const int mcols = std::max(N, max_nrhs);
   const bool blocked = d.algo == ENKF_SM_BLOCKED;
   mixed = blocked && d.dtype == ENKF_F64 && d.math != ENKF_MATH_F64;
+  // FP64 panels with FP64 refinement: the Woodbury panel update is not
+  // backward stable, a few residual corrections restore the level formula's
+  // accuracy on ill-conditioned systems
+  refine64 = blocked && d.dtype == ENKF_F64 && d.math == ENKF_MATH_F64 && d.refine_max_iter > 0;
   wdt = mixed ? ENKF_F32 : d.dtype;
   const size_t wes = dtype_size(wdt);
   if (blocked) {
@@ -96,7 +103,7 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
       for (int m = 1; m <= max_nrhs; ++m) tnp = std::max(tnp, tn_partial_elems(n, bl, m));
     }
   }
-  if (mixed)
+  if (mixed || refine64)
     for (int m = 1; m <= max_nrhs; ++m) tnp = std::max(tnp, tn_partial_elems(n, N, m));
   const size_t oTn = take(sizeof(double) * (size_t)tnp);
   // right factor of an nn product, converted: inner dimension <= N, columns <= mcols
@@ -122,6 +129,8 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   if (mixed) {
     oVw = take((size_t)ldu * N * sizeof(float));
     oZw = take((size_t)ldu * mcols * sizeof(float));
+  }
+  if (mixed || refine64) {
     oRho = take((size_t)ldu * mcols * sizeof(double));
     oNorm = take(sizeof(double) * (2 + (size_t)norm_partial_elems()));
   }
@@ -157,6 +166,8 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   if (mixed) {
     Vw = ws + oVw;
     Zw = ws + oZw;
+  }
+  if (mixed || refine64) {
     rho = reinterpret_cast<double*>(ws + oRho);
     norms = reinterpret_cast<double*>(ws + oNorm);
   }
@@ -349,7 +360,14 @@ enkf_status Plan::factor_solve_plain(int nrhs, const void* D, int64_t ldd, void*
   const int N = desc.n_ens;
   if (nrhs == 0) return factor_plain();
   if (pivot) return sweep_pivot(nrhs, D, ldd, Z, ldz);
-  if (block_r) {
+  // One loop over [U, Z] saves a launch per level, but its per-level working
+  // set, (N - k + nrhs) columns, can exceed the 256 MiB last-level (MALL)
+  // cache, while the separate U and Z loops each stay inside it when their
+  // own columns fit: then the two loops move fewer bytes from HBM.
+  const double fused_bytes = (double)(N + nrhs) * (double)n * (double)es;
+  const double split_bytes = (double)std::max(N, nrhs) * (double)n * (double)es;
+  const bool split = fused_bytes > kMallBytes && split_bytes <= kMallBytes;
+  if (block_r || split) {
     enkf_status st = factor_plain();
     return st != ENKF_SUCCESS ? st : solve_plain(nrhs, D, ldd, Z, ldz);
   }
@@ -571,7 +589,7 @@ enkf_status Plan::factor_blocked() {
     }
     if (mrest > 0) {
       NnArgs a{};
-    a.bws = Bt;
+      a.bws = Bt;
       a.n = n;
       a.K = bl;
       a.m = mrest;
@@ -660,36 +678,7 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
   const int maxit = desc.refine_max_iter;
   for (int it = 0; it <= maxit; ++it) {
     if (!sync && it == maxit) break;
-    // rho = D - (r o Z + V (V^T Z)), FP64
-    {
-      TimedLaunch tl(&timing, stream, KC_RESIDUAL, (double)(N + nrhs) * n * 8.0, 2.0 * n * N * nrhs);
-      st = launch_tn(ENKF_F64, n, N, nrhs, V, ldv, Z, ldz, G, N, tn_part, stream);
-      if (st != ENKF_SUCCESS) return st;
-    }
-    {
-      NnArgs a{};
-    a.bws = Bt;
-      a.n = n;
-      a.K = N;
-      a.m = nrhs;
-      a.A = V;
-      a.lda = ldv;
-      a.Bm = G;
-      a.ldb = N;
-      a.scale = 1.0;
-      a.Cin = Z;
-      a.ldc = ldz;
-      a.Cout = rho;
-      a.ldo = ldu;
-      a.Din = D;
-      a.ldd = ldd;
-      a.r = r;
-      TimedLaunch tl(&timing, stream, KC_RESIDUAL, (double)(N + 3 * nrhs) * n * 8.0, 2.0 * n * N * nrhs);
-      st = launch_nn(ENKF_F64, NN_RESIDUAL, a, stream);
-      if (st != ENKF_SUCCESS) return st;
-    }
-    // ||rho||^2 and ||D||^2: the convergence test and the scale of rho
-    st = launch_sumsq2(n, nrhs, rho, ldu, static_cast<const double*>(D), ldd, norms + 2, norms, stream);
+    st = residual64(nrhs, D, ldd, Z, ldz);
     if (st != ENKF_SUCCESS) return st;
     if (sync) {
       double h[2];
@@ -707,6 +696,72 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
     last.refine_iters = it + 1;
   }
   return ENKF_SUCCESS;
+}
+
+// FP64 blocked solve refined with FP64 residuals and FP64 blocked
+// corrections: Z = W~^{-1} D, then Z += W~^{-1} rho.
+enkf_status Plan::solve_refined64(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync) {
+  const int64_t n = desc.n_obs;
+  last.refine_iters = 0;
+  last.rel_residual = -1.0;
+  if (nrhs == 0) return ENKF_SUCCESS;
+  enkf_status st = solve_blocked(nrhs, D, ldd, Z, ldz);
+  if (st != ENKF_SUCCESS) return st;
+  const int maxit = desc.refine_max_iter;
+  for (int it = 0; it <= maxit; ++it) {
+    if (!sync && it == maxit) break;
+    st = residual64(nrhs, D, ldd, Z, ldz);
+    if (st != ENKF_SUCCESS) return st;
+    if (sync) {
+      double h[2];
+      ENKF_HIP_CHECK(hipMemcpyAsync(h, norms, sizeof(h), hipMemcpyDeviceToHost, stream));
+      ENKF_HIP_CHECK(hipStreamSynchronize(stream));
+      last.rel_residual = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+      if (last.rel_residual <= desc.refine_tol || it == maxit) break;
+    }
+    st = solve_blocked(nrhs, rho, ldu, rho, ldu);
+    if (st != ENKF_SUCCESS) return st;
+    st = launch_add(n, nrhs, rho, ldu, static_cast<double*>(Z), ldz, stream);
+    if (st != ENKF_SUCCESS) return st;
+    last.refine_iters = it + 1;
+  }
+  return ENKF_SUCCESS;
+}
+
+// rho = D - (r o Z + V (V^T Z)) in FP64 and the squared norms of rho and D.
+enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz) {
+  const int64_t n = desc.n_obs;
+  const int N = desc.n_ens;
+  enkf_status st;
+  {
+    TimedLaunch tl(&timing, stream, KC_RESIDUAL, (double)(N + nrhs) * n * 8.0, 2.0 * n * N * nrhs);
+    st = launch_tn(ENKF_F64, n, N, nrhs, V, ldv, Z, ldz, G, N, tn_part, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  {
+    NnArgs a{};
+    a.bws = Bt;
+    a.n = n;
+    a.K = N;
+    a.m = nrhs;
+    a.A = V;
+    a.lda = ldv;
+    a.Bm = G;
+    a.ldb = N;
+    a.scale = 1.0;
+    a.Cin = Z;
+    a.ldc = ldz;
+    a.Cout = rho;
+    a.ldo = ldu;
+    a.Din = D;
+    a.ldd = ldd;
+    a.r = r;
+    TimedLaunch tl(&timing, stream, KC_RESIDUAL, (double)(N + 3 * nrhs) * n * 8.0, 2.0 * n * N * nrhs);
+    st = launch_nn(ENKF_F64, NN_RESIDUAL, a, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  // ||rho||^2 and ||D||^2: the convergence test and the scale of rho
+  return launch_sumsq2(n, nrhs, rho, ldu, static_cast<const double*>(D), ldd, norms + 2, norms, stream);
 }
 
 // ------------------------------------------------------------------ common
@@ -732,6 +787,8 @@ enkf_status Plan::solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t l
     last.rel_residual = -1.0;
   } else if (mixed) {
     st = solve_mixed(nrhs, D, ldd, Z, ldz, info != nullptr);
+  } else if (refine64) {
+    st = solve_refined64(nrhs, D, ldd, Z, ldz, info != nullptr);
   } else {
     st = solve_blocked(nrhs, D, ldd, Z, ldz);
     last.refine_iters = 0;
@@ -741,7 +798,7 @@ enkf_status Plan::solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t l
   if (info) {
     st = get_info(info);
     if (st != ENKF_SUCCESS) return st;
-    if (mixed && desc.refine_tol > 0.0 && nrhs > 0 && !(last.rel_residual <= desc.refine_tol))
+    if ((mixed || refine64) && desc.refine_tol > 0.0 && nrhs > 0 && !(last.rel_residual <= desc.refine_tol))
     {
       char buf[96];
       snprintf(buf, sizeof(buf), "refinement stopped at relative residual %.3e after %d steps", last.rel_residual,

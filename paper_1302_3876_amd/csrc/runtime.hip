@@ -179,7 +179,8 @@ enkf_status enkf_sm_init_block_r(enkf_sm_plan* out, const enkf_sm_desc* desc, co
     if (sz > ENKF_MAX_R_BLOCK) return fail(ENKF_ERR_NOT_SUPPORTED, "init_block_r: block larger than ENKF_MAX_R_BLOCK");
   }
   if (desc->flags & ENKF_FLAG_PIVOT) return fail(ENKF_ERR_NOT_SUPPORTED, "init_block_r: pivoting needs a diagonal R");
-  if (desc->algo == ENKF_SM_BLOCKED && desc->math != (desc->dtype == ENKF_F64 ? ENKF_MATH_F64 : ENKF_MATH_F32))
+  if (desc->algo == ENKF_SM_BLOCKED &&
+      (desc->math != (desc->dtype == ENKF_F64 ? ENKF_MATH_F64 : ENKF_MATH_F32) || desc->refine_max_iter > 0))
     return fail(ENKF_ERR_NOT_SUPPORTED, "init_block_r: the refinement residual needs a diagonal R");
   Plan* p = new (std::nothrow) Plan();
   if (!p) return fail(ENKF_ERR_OUT_OF_MEMORY, "init: plan");
