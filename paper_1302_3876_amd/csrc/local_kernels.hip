@@ -4,13 +4,16 @@
 // lists of problems (longest window first, dealt to the least-loaded block).
 // Per problem, 256 threads:
 //  1. one streaming pass over the window's rows forms
-//       [A | B] = Vs^T [Vs | Ds],  Vs = R^{-1/2} V_p, Ds = R^{-1/2} D_p,
-//     on FP32 matrix cores (16x16x4); the FP32 accumulators are emptied
-//     into FP64 after every stage of rows; waves 0-1 own A, waves 2-3 own B;
-//  2. M = I + A = L D L^T in FP64 in LDS (right-looking); D holds the
-//     pivots gamma_k of the iterative formula (Section 3.3);
+//       [A | B] = (R^{-1} V_p)^T [V_p | D_p]
+//     on FP32 matrix cores (16x16x4), the next stage of rows prefetched into
+//     registers meanwhile; the FP32 accumulators are emptied into FP64 after
+//     every stage; waves 0-1 own A, waves 2-3 own B;
+//  2. M = I + A = L D L^T in FP64 registers (upper blocks of a 16 x 16
+//     thread grid, one rank-1 update per level); the pivots D are the
+//     gamma_k of the iterative formula (Section 3.3);
 //  3. y = M^{-1} delta with delta the centred ensemble row of the state
-//     point (wave 0, forward and backward substitution with shuffles);
+//     point (one wave, forward and backward substitution four rows at a
+//     time);
 //  4. since V_p^T Z_p = M^{-1} B (the Woodbury form of eq. SWM with one
 //     panel), the centre-point update is xa = x^B_s + (y^T B)/sqrt(N-1)
 //     (Section 3.1), formed by waves 2-3 from their FP64 accumulators.
@@ -52,27 +55,67 @@ struct LocalArgs {
   double inv_sqrt;
 };
 
+// 1/x to within a few ulp: the hardware estimate refined by two Newton steps
+// (each squares the relative error of the estimate).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
+// Lane k's value of a double (k uniform across the wave).
+__device__ __forceinline__ double rdlane(double v, int k) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-template <int KC>
-__global__ __launch_bounds__(LT) void local_kernel(LocalArgs a) {
-  constexpr int LDK = KC + 1;
-  __shared__ float Vt[LN * LDK];   // Vt[col][k] = V[g_k, col] / sqrt(r_{g_k})
-  __shared__ float Dt[LN * LDK];
-  __shared__ double M[LN * LDM];
-  __shared__ double rs_s[KC];
-  __shared__ double yv[LN];
+// O32: every element of V and D lies within 4 GiB of its base, so the row
+// offsets are formed in 32 bits (one offset register serves V and D).
+template <int KC, bool O32>
+__global__ __launch_bounds__(LT, KC == 32 ? 2 : 1) void local_kernel(LocalArgs a) {
+  constexpr int LDK = KC + 4;                     // float rows of the stages (16-byte aligned)
+  constexpr int PER = LN * KC / LT;               // staged elements per thread and operand
+  constexpr int CSTEP = LT / KC;                  // column step of a thread's elements
+  constexpr size_t PH1 = 3 * sizeof(float) * LN * LDK;
+  constexpr size_t PH2 = sizeof(double) * (2 * LN * LDM + 8 * LN + 7 * LN);
+  __shared__ __attribute__((aligned(16))) char smem[PH1 > PH2 ? PH1 : PH2];
+  __shared__ float xbuf[LN];                       // x^B of the state point (0 past N)
+  // phase 1: Vr[col][k] = V[g_k, col] / r_{g_k}, Vt = V, Dt = D (rows k of
+  // the stage); phase 2: M, the y partials, the shared sweep columns
+  float* Vr = reinterpret_cast<float*>(smem);
+  float* Vt = Vr + LN * LDK;
+  float* Dt = Vt + LN * LDK;
+  double* Msh = reinterpret_cast<double*>(smem);
+  double* Bsh = Msh + LN * LDM;
+  double* pan = Bsh + LN * LDM;                    // [2][4][LN] panels of four columns
+  double* piv = pan + 8 * LN;                      // the LN pivots
+  double* ipiv = piv + LN;                         // their reciprocals
+  double* yv = ipiv + LN;                          // y
+  double* ypart = yv + LN;                         // [4][LN] partial sums of y^T B
   const int t = threadIdx.x, l = t % 64, w = t / 64;
+  const int kk = t % KC, c0 = t / KC;             // this thread's stage row and first column
   const int beg = a.sched_off[blockIdx.x], end = a.sched_off[blockIdx.x + 1];
+  uint32_t coff[O32 ? PER : 1];                   // byte offsets of this thread's columns (O32)
+  if constexpr (O32) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) coff[j] = (uint32_t)(min(c0 + CSTEP * j, a.N - 1) * a.ldv) * 4u;
+  }
   for (int q = beg; q < end; ++q) {
     const int p = a.sched[q];
     const int64_t g0 = a.win_start[p], m = a.win_len[p], s = a.state_idx[p];
 
-    // 1. [A | B] over the window
+    // 1. [A | B] = (R^{-1} V_p)^T [V_p | D_p] over the window. The next
+    //    stage is loaded into registers (branch-free: rows past the window
+    //    and members past N read valid elements and are zeroed when staged)
+    //    while the matrix cores work on the current one.
     mf_f4 acc[4][2];
     double wide[4][2][4];
 #pragma unroll
@@ -83,45 +126,64 @@ __global__ __launch_bounds__(LT) void local_kernel(LocalArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) wide[ti][tj][r] = 0.0;
       }
-    for (int64_t i0 = 0; i0 < m; i0 += KC) {
-      __syncthreads();
-      if (t < KC) {
-        const int64_t i = i0 + t;
-        double v = 0.0;
-        if (i < m) {
-          int64_t g = g0 + i;
-          if (g >= a.n_glob) g -= a.n_glob;
-          const double rv = a.r[g];
-          if (!(rv > 0.0) || !__builtin_isfinite(rv)) atomicOr(a.status, kStatusNotSpd);
-          v = 1.0 / sqrt(rv);
-        }
-        rs_s[t] = v;
-      }
-      __syncthreads();
-      for (int e = t; e < KC * LN; e += LT) {
-        const int kk = e % KC, c = e / KC;
-        const int64_t i = i0 + kk;
-        float v = 0.f, d = 0.f;
-        if (i < m && c < a.N) {
-          int64_t g = g0 + i;
-          if (g >= a.n_glob) g -= a.n_glob;
-          const double sc = rs_s[kk];
-          v = (float)((double)a.V[g + (int64_t)c * a.ldv] * sc);
-          d = (float)((double)a.D[g + (int64_t)c * a.ldv] * sc);
-        }
-        Vt[c * LDK + kk] = v;
-        Dt[c * LDK + kk] = d;
-      }
-      __syncthreads();
-      const float* X = (w < 2) ? Vt : Dt;
-      const int cbase = 32 * (w % 2);
+    float vreg[PER], dreg[PER];
+    double rreg;
+    auto fetch = [&](int64_t i0) {
+      const int64_t i = min(i0 + kk, m - 1);
+      int64_t g = g0 + i;
+      if (g >= a.n_glob) g -= a.n_glob;
+      rreg = a.r[g];
+      if constexpr (O32) {
+        const uint32_t gb = (uint32_t)g * 4u;
+        const char* vb = reinterpret_cast<const char*>(a.V);
+        const char* db = reinterpret_cast<const char*>(a.D);
 #pragma unroll
-      for (int kk = 0; kk < KC; kk += 4) {
+        for (int j = 0; j < PER; ++j) {
+          const uint32_t off = gb + coff[j];
+          vreg[j] = *reinterpret_cast<const float*>(vb + off);
+          dreg[j] = *reinterpret_cast<const float*>(db + off);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          const int c = min(c0 + CSTEP * j, a.N - 1);
+          vreg[j] = a.V[g + (int64_t)c * a.ldv];
+          dreg[j] = a.D[g + (int64_t)c * a.ldv];
+        }
+      }
+    };
+    auto stash = [&](int64_t i0) {
+      const bool row_ok = i0 + kk < m;
+      if (row_ok && (!(rreg > 0.0) || !__builtin_isfinite(rreg))) atomicOr(a.status, kStatusNotSpd);
+      const double rinv = row_ok ? 1.0 / rreg : 0.0;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int c = c0 + CSTEP * j;
+        const bool ok = row_ok && c < a.N;
+        const float v = ok ? vreg[j] : 0.f;
+        Vt[c * LDK + kk] = v;
+        Vr[c * LDK + kk] = (float)((double)v * rinv);
+        Dt[c * LDK + kk] = ok ? dreg[j] : 0.f;
+      }
+    };
+    __syncthreads();                               // the previous problem is done with the LDS
+    const float xs = (w == 0 && l < a.N) ? a.XB[s + (int64_t)l * a.ldx] : 0.f;   // x^B_s, used at the end
+    fetch(0);
+    stash(0);
+    if (w == 0) xbuf[l] = xs;
+    __syncthreads();
+    const float* X = (w < 2) ? Vt : Dt;
+    const int cbase = 32 * (w % 2);
+    for (int64_t i0 = 0; i0 < m; i0 += KC) {
+      fetch(i0 + KC);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k4 = 0; k4 < KC; k4 += 4) {
         float aop[4], bop[2];
 #pragma unroll
-        for (int ti = 0; ti < 4; ++ti) aop[ti] = Vt[(16 * ti + l % 16) * LDK + kk + l / 16];
+        for (int ti = 0; ti < 4; ++ti) aop[ti] = Vr[(16 * ti + l % 16) * LDK + k4 + l / 16];
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj) bop[tj] = X[(cbase + 16 * tj + l % 16) * LDK + kk + l / 16];
+        for (int tj = 0; tj < 2; ++tj) bop[tj] = X[(cbase + 16 * tj + l % 16) * LDK + k4 + l / 16];
 #pragma unroll
         for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
@@ -136,10 +198,23 @@ __global__ __launch_bounds__(LT) void local_kernel(LocalArgs a) {
           for (int r = 0; r < 4; ++r) wide[ti][tj][r] += (double)acc[ti][tj][r];
           acc[ti][tj] = mf_f4{0.f, 0.f, 0.f, 0.f};
         }
+      __builtin_amdgcn_sched_barrier(0);
+      __syncthreads();
+      stash(i0 + KC);                             // after the last stage: zeros, unused
+      __syncthreads();
     }
-    __syncthreads();
-    // 2. M = I + A, then L D L^T
-    if (w < 2) {
+    // 2. M = I + A (waves 0-1 hold A, waves 2-3 hold B; both go to the LDS),
+    //    redistributed to a 16 x 16 thread grid: thread (gi, gj) keeps the
+    //    elements (gi + 16 r, gj + 16 c), c >= r, of the upper blocks. Right-
+    //    looking M = L D L^T four levels at a time: the panel P of columns
+    //    k0 .. k0+3 (published in the LDS) has the diagonal block
+    //    P_d = L4 D4 L4^T; every kept element takes M -= (L4^{-1} P_i)^T
+    //    D4^{-1} (L4^{-1} P_j), which equals the four single-level updates
+    //    c c^T / d; D4 holds the pivots gamma_k0 .. gamma_k0+3 of the
+    //    iterative formula (Section 3.3) and L4^{-1} P_i the columns of L D.
+    //    Elements of finished rows take rounding-size values no step reads.
+    {
+      double* dstm = (w < 2) ? Msh : Bsh;
 #pragma unroll
       for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
@@ -147,65 +222,174 @@ __global__ __launch_bounds__(LT) void local_kernel(LocalArgs a) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = 16 * ti + 4 * (l / 16) + r;
-            const int col = 32 * w + 16 * tj + l % 16;
-            M[row * LDM + col] = wide[ti][tj][r] + (row == col ? 1.0 : 0.0);
+            const int col = 32 * (w % 2) + 16 * tj + l % 16;
+            dstm[row * LDM + col] = wide[ti][tj][r] + ((w < 2 && row == col) ? 1.0 : 0.0);
           }
     }
     __syncthreads();
-    for (int j = 0; j < LN; ++j) {
-      const double d = M[j * LDM + j];
-      const double inv_d = 1.0 / d;
-      if (t == 0 && j < a.N) {
-        if (a.gamma) a.gamma[p + (int64_t)j * a.n_prob] = d;
-        if (!(d > 0.0) || !__builtin_isfinite(d)) atomicOr(a.status, kStatusNotSpd);
+    const int gi = t % 16, gj = t / 16;
+    double mv[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = r; c < 4; ++c) mv[r][c] = Msh[(gi + 16 * r) * LDM + gj + 16 * c];
+    pan[(t / LN) * LN + t % LN] = Msh[(t / LN) * LDM + t % LN];   // panel 0 = rows 0..3
+    __syncthreads();
+    auto ldl_phase = [&](auto kb_c) {
+      constexpr int KB = decltype(kb_c)::value;
+#pragma unroll 1
+      for (int ss = 0; ss < 4; ++ss) {
+        const int k0 = 16 * KB + 4 * ss;
+        const double* P = pan + (ss & 1) * 4 * LN;
+        double* Pn = pan + ((ss + 1) & 1) * 4 * LN;
+        double Lm[4][4], dv[4], iv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double e = P[q * LN + k0 + q];
+#pragma unroll
+          for (int u = 0; u < q; ++u) e -= Lm[q][u] * Lm[q][u] * dv[u];
+          dv[q] = e;
+          iv[q] = recip(e);
+#pragma unroll
+          for (int v = q + 1; v < 4; ++v) {
+            double f = P[q * LN + k0 + v];
+#pragma unroll
+            for (int u = 0; u < q; ++u) f -= Lm[v][u] * Lm[q][u] * dv[u];
+            Lm[v][q] = f * iv[q];
+          }
+        }
+        double ch[4][4];                           // rows: L4^{-1} P_i (then scaled by D4^{-1})
+#pragma unroll
+        for (int r = KB; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            double x = P[q * LN + gi + 16 * r];
+#pragma unroll
+            for (int u = 0; u < q; ++u) x -= Lm[q][u] * ch[r][u];
+            ch[r][q] = x;
+          }
+        if (gj == 0)                               // columns k0..k0+3 of L D
+#pragma unroll
+          for (int r = KB; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Msh[(k0 + q) * LDM + gi + 16 * r] = ch[r][q];
+#pragma unroll
+        for (int r = KB; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) ch[r][q] *= iv[q];
+        double cj[4][4];                           // columns: L4^{-1} P_j
+#pragma unroll
+        for (int c = KB; c < 4; ++c)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            double x = P[q * LN + gj + 16 * c];
+#pragma unroll
+            for (int u = 0; u < q; ++u) x -= Lm[q][u] * cj[c][u];
+            cj[c][q] = x;
+          }
+#pragma unroll
+        for (int r = KB; r < 4; ++r)
+#pragma unroll
+          for (int c = r; c < 4; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) mv[r][c] -= ch[r][q] * cj[c][q];
+        if (t == 0)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            piv[k0 + q] = dv[q];
+            ipiv[k0 + q] = iv[q];
+          }
+        const int q = gi - (k0 + 4) % 16;           // next panel: rows k0+4 .. k0+7
+        if (k0 + 4 < LN && q >= 0 && q < 4) {
+          if (ss < 3) {
+#pragma unroll
+            for (int c = KB; c < 4; ++c) Pn[q * LN + gj + 16 * c] = mv[KB][c];
+          } else {
+            if constexpr (KB < 3) {
+#pragma unroll
+              for (int c = KB + 1; c < 4; ++c) Pn[q * LN + gj + 16 * c] = mv[KB + 1][c];
+            }
+          }
+        }
+        __syncthreads();
       }
-      const int nr = LN - j - 1;
-      for (int e = t; e < nr * nr; e += LT) {
-        const int i = j + 1 + e / nr, k = j + 1 + e % nr;
-        if (k <= i) M[i * LDM + k] -= M[i * LDM + j] * M[k * LDM + j] * inv_d;
-      }
-      __syncthreads();
-      for (int i = j + 1 + t; i < LN; i += LT) M[i * LDM + j] *= inv_d;
-      __syncthreads();
+    };
+    ldl_phase(std::integral_constant<int, 0>{});
+    ldl_phase(std::integral_constant<int, 1>{});
+    ldl_phase(std::integral_constant<int, 2>{});
+    ldl_phase(std::integral_constant<int, 3>{});
+    if (t < a.N) {
+      const double d = piv[t];
+      if (a.gamma) a.gamma[p + (int64_t)t * a.n_prob] = d;
+      if (!(d > 0.0) || !__builtin_isfinite(d)) atomicOr(a.status, kStatusNotSpd);
     }
-    // 3. y = M^{-1} delta (wave 0)
+    // 3. y = M^{-1} delta = L^{-T} D^{-1} L^{-1} delta, delta the centred
+    //    ensemble row of the state point, four rows at a time (wave 0, lane i
+    //    holds entry i; L[i][k] = Msh[k][i] / d_k for i > k).
     if (w == 0) {
-      const double x = (l < a.N) ? (double)a.XB[s + (int64_t)l * a.ldx] : 0.0;
+      const double x = (double)xbuf[l];
       const double mean = wsum(x) / (double)a.N;
       double z = (l < a.N) ? x - mean : 0.0;
-      for (int k = 0; k < LN; ++k) {
-        const double zk = __shfl(z, k, 64);
-        if (l > k) z -= M[l * LDM + k] * zk;
+#pragma unroll 2
+      for (int k0 = 0; k0 < LN; k0 += 4) {        // forward: z = L^{-1} delta
+        double zp[4], f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double v = rdlane(z, k0 + q);
+#pragma unroll
+          for (int u = 0; u < q; ++u) v -= Msh[(k0 + u) * LDM + k0 + q] * f[u];
+          zp[q] = v;
+          f[q] = v * ipiv[k0 + q];
+        }
+        double acc_z = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc_z += Msh[(k0 + q) * LDM + l] * f[q];
+        const int dq = l - k0;
+        const double zin = dq == 0 ? zp[0] : dq == 1 ? zp[1] : dq == 2 ? zp[2] : zp[3];
+        z = (l > k0 + 3) ? z - acc_z : (dq >= 0 ? zin : z);
       }
-      z = z / M[l * LDM + l];
-      for (int k = LN - 1; k >= 0; --k) {
-        const double yk = __shfl(z, k, 64);
-        if (l < k) z -= M[k * LDM + l] * yk;
+      double y = z * ipiv[l];                     // D^{-1} z, then y = L^{-T} (D^{-1} z)
+#pragma unroll 2
+      for (int k0 = LN - 4; k0 >= 0; k0 -= 4) {
+        double yp[4];
+#pragma unroll
+        for (int q = 3; q >= 0; --q) {
+          double v = rdlane(y, k0 + q);
+#pragma unroll
+          for (int u = q + 1; u < 4; ++u) v -= Msh[(k0 + q) * LDM + k0 + u] * ipiv[k0 + q] * yp[u];
+          yp[q] = v;
+        }
+        double acc_y = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc_y += Msh[l * LDM + k0 + q] * yp[q];
+        const int dq = l - k0;
+        const double yin = dq == 0 ? yp[0] : dq == 1 ? yp[1] : dq == 2 ? yp[2] : yp[3];
+        y = (l < k0) ? y - acc_y * ipiv[l] : (dq <= 3 ? yin : y);
       }
-      yv[l] = z;
+      yv[l] = y;
     }
     __syncthreads();
-    // 4. xa = x^B_s + (y^T B) / sqrt(N-1) (waves 2-3 hold B)
-    if (w >= 2) {
+    // 4. xa = x^B_s + (y^T B) / sqrt(N-1): each wave sums a quarter of the rows
+    {
+      double part = 0.0;
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
-        double part = 0.0;
-#pragma unroll
-        for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) part += yv[16 * ti + 4 * (l / 16) + r] * wide[ti][tj][r];
-        part += __shfl_xor(part, 16, 64);
-        part += __shfl_xor(part, 32, 64);
-        const int col = 32 * (w - 2) + 16 * tj + l;
-        if (l < 16 && col < a.N)
-          a.XA[p + (int64_t)col * a.ldxa] = (float)((double)a.XB[s + (int64_t)col * a.ldx] + part * a.inv_sqrt);
-      }
+      for (int i = 16 * w; i < 16 * w + 16; ++i) part += yv[i] * Bsh[i * LDM + l];
+      ypart[w * LN + l] = part;
+    }
+    __syncthreads();
+    if (w == 0 && l < a.N) {
+      const double part = (ypart[l] + ypart[LN + l]) + (ypart[2 * LN + l] + ypart[3 * LN + l]);
+      a.XA[p + (int64_t)l * a.ldxa] = (float)((double)xbuf[l] + part * a.inv_sqrt);
     }
   }
 }
 
-const void* kernel_for(int kc) {
-  return kc == 64 ? reinterpret_cast<const void*>(&local_kernel<64>) : reinterpret_cast<const void*>(&local_kernel<32>);
+const void* kernel_for(int kc, bool o32) {
+  if (o32)
+    return kc == 64 ? reinterpret_cast<const void*>(&local_kernel<64, true>)
+                    : reinterpret_cast<const void*>(&local_kernel<32, true>);
+  return kc == 64 ? reinterpret_cast<const void*>(&local_kernel<64, false>)
+                  : reinterpret_cast<const void*>(&local_kernel<32, false>);
 }
 
 }  // namespace
@@ -225,7 +409,9 @@ struct LocalPlan {
   int n_cu = 256;
   int max_blocks = 0;
   int kc = 32;
+  bool o32 = true;
   int nblocks = 0;
+  const void* graph_func = nullptr;
   bool tuned = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -261,7 +447,9 @@ enkf_status LocalPlan::set_config(int kc_, int blocks_per_cu) {
     LB top = heap.top();
     heap.pop();
     lists[top.second].push_back(pidx);
-    heap.push({top.first + len_h[pidx] + 2 * LN, top.second});
+    // cost in row-stage units: the streamed rows (whole stages) plus the
+    // factorization and solves, which take about as long as 5 LN rows
+    heap.push({top.first + (len_h[pidx] + kc_ - 1) / kc_ * kc_ + 5 * LN, top.second});
   }
   std::vector<int32_t> flat;
   std::vector<int32_t> off(nb + 1, 0);
@@ -279,8 +467,8 @@ enkf_status LocalPlan::set_config(int kc_, int blocks_per_cu) {
 }
 
 enkf_status LocalPlan::launch_direct() {
-  if (kc == 64) local_kernel<64><<<nblocks, LT, 0, stream>>>(args);
-  else local_kernel<32><<<nblocks, LT, 0, stream>>>(args);
+  hipLaunchKernelGGL(reinterpret_cast<void (*)(LocalArgs)>(const_cast<void*>(kernel_for(kc, o32))), dim3(nblocks),
+                     dim3(LT), 0, stream, args);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
@@ -297,7 +485,8 @@ enkf_status LocalPlan::build_graph() {
   ENKF_HIP_CHECK(hipGraphCreate(&graph, 0));
   hipKernelNodeParams kp{};
   void* kargs[] = {&args};
-  kp.func = const_cast<void*>(kernel_for(kc));
+  kp.func = const_cast<void*>(kernel_for(kc, o32));
+  graph_func = kp.func;
   kp.gridDim = dim3(nblocks);
   kp.blockDim = dim3(LT);
   kp.sharedMemBytes = 0;
@@ -405,6 +594,8 @@ enkf_status enkf_local_analysis(enkf_local_plan plan, const double* r, const flo
   a.sched_off = pl->sched_off;
   a.status = pl->status;
   a.inv_sqrt = 1.0 / std::sqrt((double)(d.n_ens - 1));
+  // byte offset of the last element of V and D
+  pl->o32 = (uint64_t)(d.n_glob - 1 + (int64_t)(d.n_ens - 1) * ldv) * 4u <= (uint64_t)UINT32_MAX;
   enkf_status st;
   if (!pl->tuned) {
     // time every configuration on this data and keep the fastest
@@ -444,13 +635,13 @@ enkf_status enkf_local_analysis(enkf_local_plan plan, const double* r, const flo
     if (st != ENKF_SUCCESS) return st;
     pl->tuned = true;
   }
-  if (!pl->exec) {
+  if (!pl->exec || pl->graph_func != kernel_for(pl->kc, pl->o32)) {
     st = pl->build_graph();
     if (st != ENKF_SUCCESS) return st;
   } else {
     hipKernelNodeParams kp{};
     void* kargs[] = {&pl->args};
-    kp.func = const_cast<void*>(kernel_for(pl->kc));
+    kp.func = const_cast<void*>(kernel_for(pl->kc, pl->o32));
     kp.gridDim = dim3(pl->nblocks);
     kp.blockDim = dim3(LT);
     kp.sharedMemBytes = 0;
