@@ -13,9 +13,12 @@
  * Each local solve is the Sherman-Morrison-Woodbury form (eq. SWM) with one
  * panel of all N levels: M_p = I + V_p^T R_p^{-1} V_p = L D L^T, whose
  * pivots D are the gamma_k of the iterative formula (Section 3.3), and
- * V_p^T Z_p = M_p^{-1} V_p^T R_p^{-1} D_p. Products run on FP32 matrix cores
- * (FP32 storage) with FP64 accumulation across row stages; the pivots and
- * the N x N solves are FP64.
+ * V_p^T Z_p = M_p^{-1} V_p^T R_p^{-1} D_p, so that
+ * xa_p = x^B_s + (R_p^{-1} V_p y)^T D_p / sqrt(N-1) with y = M_p^{-1} delta_s,
+ * delta_s the centred ensemble row of X^B at s. The Gram product
+ * V_p^T R_p^{-1} V_p runs on FP32 matrix cores (FP32 storage) with FP64
+ * accumulation across row stages; the pivots, the N x N solve and the second
+ * pass over the window forming (R_p^{-1} V_p y)^T D_p are FP64 arithmetic.
  *
  * Conventions as in enkf_sm.h: column-major, device pointers, stream-ordered,
  * enkf_status returns; argument errors are found on the host.

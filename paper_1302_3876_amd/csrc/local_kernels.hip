@@ -4,19 +4,20 @@
 // lists of problems (longest window first, dealt to the least-loaded block).
 // Per problem, 256 threads:
 //  1. one streaming pass over the window's rows forms
-//       [A | B] = (R^{-1} V_p)^T [V_p | D_p]
+//       A = (R^{-1} V_p)^T V_p
 //     on FP32 matrix cores (16x16x4), the next stage of rows prefetched into
 //     registers meanwhile; the FP32 accumulators are emptied into FP64 after
-//     every stage; waves 0-1 own A, waves 2-3 own B;
+//     every stage;
 //  2. M = I + A = L D L^T in FP64 registers (upper blocks of a 16 x 16
 //     thread grid, one rank-1 update per level); the pivots D are the
 //     gamma_k of the iterative formula (Section 3.3);
 //  3. y = M^{-1} delta with delta the centred ensemble row of the state
 //     point (one wave, forward and backward substitution four rows at a
 //     time);
-//  4. since V_p^T Z_p = M^{-1} B (the Woodbury form of eq. SWM with one
-//     panel), the centre-point update is xa = x^B_s + (y^T B)/sqrt(N-1)
-//     (Section 3.1), formed by waves 2-3 from their FP64 accumulators.
+//  4. since V_p^T Z_p = M^{-1} (R^{-1} V_p)^T D_p (the Woodbury form of
+//     eq. SWM with one panel), the centre-point update (Section 3.1) is
+//     xa = x^B_s + (R^{-1} V_p y)^T D_p / sqrt(N-1), formed by a second,
+//     O(n_p N) pass over the window.
 // The ensemble is padded to 64 members (zero anomalies give identity rows of
 // M and zero products).
 #include <algorithm>
@@ -80,77 +81,79 @@ __device__ __forceinline__ double wsum(double v) {
 // O32: every element of V and D lies within 4 GiB of its base, so the row
 // offsets are formed in 32 bits (one offset register serves V and D).
 template <int KC, bool O32>
-__global__ __launch_bounds__(LT, KC == 32 ? 2 : 1) void local_kernel(LocalArgs a) {
-  constexpr int LDK = KC + 4;                     // float rows of the stages (16-byte aligned)
-  constexpr int PER = LN * KC / LT;               // staged elements per thread and operand
-  constexpr int CSTEP = LT / KC;                  // column step of a thread's elements
-  constexpr size_t PH1 = 3 * sizeof(float) * LN * LDK;
-  constexpr size_t PH2 = sizeof(double) * (2 * LN * LDM + 8 * LN + 7 * LN);
-  __shared__ __attribute__((aligned(16))) char smem[PH1 > PH2 ? PH1 : PH2];
+__global__ __launch_bounds__(LT, KC == 32 ? 3 : 2) void local_kernel(LocalArgs a) {
+  constexpr int LDK = KC + 4;                     // float rows of the Gram stages (16-byte aligned)
+  constexpr int PER = LN * KC / LT;               // Gram: staged elements per thread
+  constexpr int CSTEP = LT / KC;                  // Gram: column step of a thread's elements
+  constexpr int K4 = 64;                          // rows per stage of the second pass (one per lane)
+  constexpr int PER4 = LN / 4;                    // second pass: members per thread
+  constexpr int LD4D = K4 + 1;                    // rows of the final transposition
+  constexpr size_t PH1 = 2 * sizeof(float) * LN * LDK;
+  constexpr size_t PH2 = sizeof(double) * (LN * LDM + 8 * LN + 2 * LN);
+  constexpr size_t PH4 = sizeof(double) * (LN * LD4D + 2 * 4 * K4 + 4 * LN);
+  constexpr size_t SM = PH1 > PH2 ? (PH1 > PH4 ? PH1 : PH4) : (PH2 > PH4 ? PH2 : PH4);
+  __shared__ __attribute__((aligned(16))) char smem[SM];
   __shared__ float xbuf[LN];                       // x^B of the state point (0 past N)
-  // phase 1: Vr[col][k] = V[g_k, col] / r_{g_k}, Vt = V, Dt = D (rows k of
-  // the stage); phase 2: M, the y partials, the shared sweep columns
+  __shared__ double yv[LN];                        // y = M^{-1} delta (0 past N)
+  __shared__ double zv[LN];                        // delta under forward elimination
+  __shared__ double zf[LN];                        // z = L^{-1} delta
+  // phase 1: Vr[col][k] = V[g_k, col] / r_{g_k} and Vt = V (rows k of the
+  // stage); phase 2: M (then the columns of L D), the panels, the pivots and
+  // their reciprocals; phase 4: partial sums
   float* Vr = reinterpret_cast<float*>(smem);
   float* Vt = Vr + LN * LDK;
-  float* Dt = Vt + LN * LDK;
   double* Msh = reinterpret_cast<double*>(smem);
-  double* Bsh = Msh + LN * LDM;
-  double* pan = Bsh + LN * LDM;                    // [2][4][LN] panels of four columns
+  double* pan = Msh + LN * LDM;                    // [2][4][LN] panels of four columns
   double* piv = pan + 8 * LN;                      // the LN pivots
   double* ipiv = piv + LN;                         // their reciprocals
-  double* yv = ipiv + LN;                          // y
-  double* ypart = yv + LN;                         // [4][LN] partial sums of y^T B
+  double* ored = reinterpret_cast<double*>(smem);  // [LN][LD4D] lane sums of s_i D_i
+  double* wpart = ored + LN * LD4D;                // [2][4][K4] partial dots V_i . y
+  double* opart = wpart + 2 * 4 * K4;              // [4][LN]
   const int t = threadIdx.x, l = t % 64, w = t / 64;
-  const int kk = t % KC, c0 = t / KC;             // this thread's stage row and first column
+  const int kk = t % KC, c0 = t / KC;             // Gram: this thread's stage row and first column
   const int beg = a.sched_off[blockIdx.x], end = a.sched_off[blockIdx.x + 1];
-  uint32_t coff[O32 ? PER : 1];                   // byte offsets of this thread's columns (O32)
+  uint32_t coff[O32 ? PER : 1];                   // byte offsets of this thread's Gram columns (O32)
+  uint32_t coff4[O32 ? PER4 : 1];                 // and of its second-pass columns
   if constexpr (O32) {
 #pragma unroll
     for (int j = 0; j < PER; ++j) coff[j] = (uint32_t)(min(c0 + CSTEP * j, a.N - 1) * a.ldv) * 4u;
+#pragma unroll
+    for (int j = 0; j < PER4; ++j) coff4[j] = (uint32_t)(min(w + 4 * j, a.N - 1) * a.ldv) * 4u;
   }
+  // element (g, column c) of V or D, c the thread's j-th column of a pass
+  auto ld = [&](const float* base, int64_t g, int c, uint32_t off) -> float {
+    if constexpr (O32)
+      return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + ((uint32_t)g * 4u + off));
+    else
+      return base[g + (int64_t)min(c, a.N - 1) * a.ldv];
+  };
   for (int q = beg; q < end; ++q) {
     const int p = a.sched[q];
     const int64_t g0 = a.win_start[p], m = a.win_len[p], s = a.state_idx[p];
+    auto row_of = [&](int64_t i) -> int64_t {     // global row of window row i (clamped to the window)
+      int64_t g = g0 + min(i, m - 1);
+      return g >= a.n_glob ? g - a.n_glob : g;
+    };
 
-    // 1. [A | B] = (R^{-1} V_p)^T [V_p | D_p] over the window. The next
-    //    stage is loaded into registers (branch-free: rows past the window
-    //    and members past N read valid elements and are zeroed when staged)
-    //    while the matrix cores work on the current one.
-    mf_f4 acc[4][2];
-    double wide[4][2][4];
+    // 1. A = (R^{-1} V_p)^T V_p over the window. The next stage is loaded
+    //    into registers (branch-free: rows past the window and members past
+    //    N read valid elements and are zeroed when staged) while the matrix
+    //    cores work on the current one. Wave w forms rows 16w .. 16w+15.
+    mf_f4 acc[4];
+    double wide[4][4];
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti)
+    for (int tj = 0; tj < 4; ++tj) {
+      acc[tj] = mf_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
-        acc[ti][tj] = mf_f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int r = 0; r < 4; ++r) wide[ti][tj][r] = 0.0;
-      }
-    float vreg[PER], dreg[PER];
+      for (int r = 0; r < 4; ++r) wide[tj][r] = 0.0;
+    }
+    float vreg[PER];
     double rreg;
     auto fetch = [&](int64_t i0) {
-      const int64_t i = min(i0 + kk, m - 1);
-      int64_t g = g0 + i;
-      if (g >= a.n_glob) g -= a.n_glob;
+      const int64_t g = row_of(i0 + kk);
       rreg = a.r[g];
-      if constexpr (O32) {
-        const uint32_t gb = (uint32_t)g * 4u;
-        const char* vb = reinterpret_cast<const char*>(a.V);
-        const char* db = reinterpret_cast<const char*>(a.D);
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-          const uint32_t off = gb + coff[j];
-          vreg[j] = *reinterpret_cast<const float*>(vb + off);
-          dreg[j] = *reinterpret_cast<const float*>(db + off);
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-          const int c = min(c0 + CSTEP * j, a.N - 1);
-          vreg[j] = a.V[g + (int64_t)c * a.ldv];
-          dreg[j] = a.D[g + (int64_t)c * a.ldv];
-        }
-      }
+      for (int j = 0; j < PER; ++j) vreg[j] = ld(a.V, g, c0 + CSTEP * j, O32 ? coff[j] : 0u);
     };
     auto stash = [&](int64_t i0) {
       const bool row_ok = i0 + kk < m;
@@ -159,11 +162,9 @@ __global__ __launch_bounds__(LT, KC == 32 ? 2 : 1) void local_kernel(LocalArgs a
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const int c = c0 + CSTEP * j;
-        const bool ok = row_ok && c < a.N;
-        const float v = ok ? vreg[j] : 0.f;
+        const float v = (row_ok && c < a.N) ? vreg[j] : 0.f;
         Vt[c * LDK + kk] = v;
         Vr[c * LDK + kk] = (float)((double)v * rinv);
-        Dt[c * LDK + kk] = ok ? dreg[j] : 0.f;
       }
     };
     __syncthreads();                               // the previous problem is done with the LDS
@@ -172,60 +173,47 @@ __global__ __launch_bounds__(LT, KC == 32 ? 2 : 1) void local_kernel(LocalArgs a
     stash(0);
     if (w == 0) xbuf[l] = xs;
     __syncthreads();
-    const float* X = (w < 2) ? Vt : Dt;
-    const int cbase = 32 * (w % 2);
     for (int64_t i0 = 0; i0 < m; i0 += KC) {
       fetch(i0 + KC);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int k4 = 0; k4 < KC; k4 += 4) {
-        float aop[4], bop[2];
+        const float aop = Vr[(16 * w + l % 16) * LDK + k4 + l / 16];
+        float bop[4];
 #pragma unroll
-        for (int ti = 0; ti < 4; ++ti) aop[ti] = Vr[(16 * ti + l % 16) * LDK + k4 + l / 16];
+        for (int tj = 0; tj < 4; ++tj) bop[tj] = Vt[(16 * tj + l % 16) * LDK + k4 + l / 16];
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj) bop[tj] = X[(cbase + 16 * tj + l % 16) * LDK + k4 + l / 16];
-#pragma unroll
-        for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-          for (int tj = 0; tj < 2; ++tj)
-            acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[ti], bop[tj], acc[ti][tj], 0, 0, 0);
+        for (int tj = 0; tj < 4; ++tj) acc[tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[tj], acc[tj], 0, 0, 0);
       }
 #pragma unroll
-      for (int ti = 0; ti < 4; ++ti)
+      for (int tj = 0; tj < 4; ++tj) {
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) wide[ti][tj][r] += (double)acc[ti][tj][r];
-          acc[ti][tj] = mf_f4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int r = 0; r < 4; ++r) wide[tj][r] += (double)acc[tj][r];
+        acc[tj] = mf_f4{0.f, 0.f, 0.f, 0.f};
+      }
       __builtin_amdgcn_sched_barrier(0);
       __syncthreads();
       stash(i0 + KC);                             // after the last stage: zeros, unused
       __syncthreads();
     }
-    // 2. M = I + A (waves 0-1 hold A, waves 2-3 hold B; both go to the LDS),
-    //    redistributed to a 16 x 16 thread grid: thread (gi, gj) keeps the
-    //    elements (gi + 16 r, gj + 16 c), c >= r, of the upper blocks. Right-
-    //    looking M = L D L^T four levels at a time: the panel P of columns
-    //    k0 .. k0+3 (published in the LDS) has the diagonal block
-    //    P_d = L4 D4 L4^T; every kept element takes M -= (L4^{-1} P_i)^T
-    //    D4^{-1} (L4^{-1} P_j), which equals the four single-level updates
-    //    c c^T / d; D4 holds the pivots gamma_k0 .. gamma_k0+3 of the
-    //    iterative formula (Section 3.3) and L4^{-1} P_i the columns of L D.
-    //    Elements of finished rows take rounding-size values no step reads.
-    {
-      double* dstm = (w < 2) ? Msh : Bsh;
+    // 2. M = I + A to the LDS, redistributed to a 16 x 16 thread grid: thread
+    //    (gi, gj) keeps the elements (gi + 16 r, gj + 16 c), c >= r, of the
+    //    upper blocks. Right-looking M = L D L^T four levels at a time: the
+    //    panel P of columns k0 .. k0+3 (published in the LDS) has the diagonal
+    //    block P_d = L4 D4 L4^T; every kept element takes
+    //    M -= (L4^{-1} P_i)^T D4^{-1} (L4^{-1} P_j), which equals the four
+    //    single-level updates c c^T / d; D4 holds the pivots gamma_k0 ..
+    //    gamma_k0+3 of the iterative formula (Section 3.3) and L4^{-1} P_i the
+    //    columns of L D. Elements of finished rows take rounding-size values
+    //    no step reads.
 #pragma unroll
-      for (int ti = 0; ti < 4; ++ti)
+    for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * ti + 4 * (l / 16) + r;
-            const int col = 32 * (w % 2) + 16 * tj + l % 16;
-            dstm[row * LDM + col] = wide[ti][tj][r] + ((w < 2 && row == col) ? 1.0 : 0.0);
-          }
-    }
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * w + 4 * (l / 16) + r;
+        const int col = 16 * tj + l % 16;
+        Msh[row * LDM + col] = wide[tj][r] + (row == col ? 1.0 : 0.0);
+      }
     __syncthreads();
     const int gi = t % 16, gj = t / 16;
     double mv[4][4];
@@ -234,6 +222,11 @@ __global__ __launch_bounds__(LT, KC == 32 ? 2 : 1) void local_kernel(LocalArgs a
 #pragma unroll
       for (int c = r; c < 4; ++c) mv[r][c] = Msh[(gi + 16 * r) * LDM + gj + 16 * c];
     pan[(t / LN) * LN + t % LN] = Msh[(t / LN) * LDM + t % LN];   // panel 0 = rows 0..3
+    if (w == 0) {                                  // delta, the centred ensemble row of the state point
+      const double x = (double)xbuf[l];
+      const double mean = wsum(x) / (double)a.N;
+      zv[l] = (l < a.N) ? x - mean : 0.0;
+    }
     __syncthreads();
     auto ldl_phase = [&](auto kb_c) {
       constexpr int KB = decltype(kb_c)::value;
@@ -244,70 +237,93 @@ __global__ __launch_bounds__(LT, KC == 32 ? 2 : 1) void local_kernel(LocalArgs a
         double* Pn = pan + ((ss + 1) & 1) * 4 * LN;
         double Lm[4][4], dv[4], iv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          double e = P[q * LN + k0 + q];
+        for (int qq = 0; qq < 4; ++qq) {
+          double e = P[qq * LN + k0 + qq];
 #pragma unroll
-          for (int u = 0; u < q; ++u) e -= Lm[q][u] * Lm[q][u] * dv[u];
-          dv[q] = e;
-          iv[q] = recip(e);
+          for (int u = 0; u < qq; ++u) e -= Lm[qq][u] * Lm[qq][u] * dv[u];
+          dv[qq] = e;
+          iv[qq] = recip(e);
 #pragma unroll
-          for (int v = q + 1; v < 4; ++v) {
-            double f = P[q * LN + k0 + v];
+          for (int v = qq + 1; v < 4; ++v) {
+            double f = P[qq * LN + k0 + v];
 #pragma unroll
-            for (int u = 0; u < q; ++u) f -= Lm[v][u] * Lm[q][u] * dv[u];
-            Lm[v][q] = f * iv[q];
+            for (int u = 0; u < qq; ++u) f -= Lm[v][u] * Lm[qq][u] * dv[u];
+            Lm[v][qq] = f * iv[qq];
           }
         }
         double ch[4][4];                           // rows: L4^{-1} P_i (then scaled by D4^{-1})
 #pragma unroll
         for (int r = KB; r < 4; ++r)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            double x = P[q * LN + gi + 16 * r];
+          for (int qq = 0; qq < 4; ++qq) {
+            double x = P[qq * LN + gi + 16 * r];
 #pragma unroll
-            for (int u = 0; u < q; ++u) x -= Lm[q][u] * ch[r][u];
-            ch[r][q] = x;
+            for (int u = 0; u < qq; ++u) x -= Lm[qq][u] * ch[r][u];
+            ch[r][qq] = x;
           }
         if (gj == 0)                               // columns k0..k0+3 of L D
 #pragma unroll
           for (int r = KB; r < 4; ++r)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Msh[(k0 + q) * LDM + gi + 16 * r] = ch[r][q];
+            for (int qq = 0; qq < 4; ++qq) Msh[(k0 + qq) * LDM + gi + 16 * r] = ch[r][qq];
 #pragma unroll
         for (int r = KB; r < 4; ++r)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) ch[r][q] *= iv[q];
-        double cj[4][4];                           // columns: L4^{-1} P_j
+          for (int qq = 0; qq < 4; ++qq) ch[r][qq] *= iv[qq];
+        // forward elimination of delta: the panel's entries become
+        // L4^{-1} delta_P (final entries of z = L^{-1} delta); later rows take
+        // the same rank-4 update as M
+        double zh[4];
 #pragma unroll
-        for (int c = KB; c < 4; ++c)
+        for (int qq = 0; qq < 4; ++qq) {
+          double v = zv[k0 + qq];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            double x = P[q * LN + gj + 16 * c];
+          for (int u = 0; u < qq; ++u) v -= Lm[qq][u] * zh[u];
+          zh[qq] = v;
+        }
+        if (gj == 0) {
 #pragma unroll
-            for (int u = 0; u < q; ++u) x -= Lm[q][u] * cj[c][u];
-            cj[c][q] = x;
+          for (int r = KB; r < 4; ++r) {
+            const int i = gi + 16 * r;
+            double v = zv[i];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) v -= ch[r][qq] * zh[qq];
+            if (r > KB || i > k0 + 3) zv[i] = v;
           }
-#pragma unroll
-        for (int r = KB; r < 4; ++r)
-#pragma unroll
-          for (int c = r; c < 4; ++c)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) mv[r][c] -= ch[r][q] * cj[c][q];
+        }
         if (t == 0)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            piv[k0 + q] = dv[q];
-            ipiv[k0 + q] = iv[q];
+          for (int qq = 0; qq < 4; ++qq) zf[k0 + qq] = zh[qq];
+#pragma unroll
+        for (int c = KB; c < 4; ++c) {             // column block c: L4^{-1} P_j, then its elements
+          double cj[4];
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            double x = P[qq * LN + gj + 16 * c];
+#pragma unroll
+            for (int u = 0; u < qq; ++u) x -= Lm[qq][u] * cj[u];
+            cj[qq] = x;
           }
-        const int q = gi - (k0 + 4) % 16;           // next panel: rows k0+4 .. k0+7
-        if (k0 + 4 < LN && q >= 0 && q < 4) {
+#pragma unroll
+          for (int r = KB; r <= c; ++r)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) mv[r][c] -= ch[r][qq] * cj[qq];
+        }
+        if (t == 0)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            piv[k0 + qq] = dv[qq];
+            ipiv[k0 + qq] = iv[qq];
+          }
+        const int qn = gi - (k0 + 4) % 16;         // next panel: rows k0+4 .. k0+7
+        if (k0 + 4 < LN && qn >= 0 && qn < 4) {
           if (ss < 3) {
 #pragma unroll
-            for (int c = KB; c < 4; ++c) Pn[q * LN + gj + 16 * c] = mv[KB][c];
+            for (int c = KB; c < 4; ++c) Pn[qn * LN + gj + 16 * c] = mv[KB][c];
           } else {
             if constexpr (KB < 3) {
 #pragma unroll
-              for (int c = KB + 1; c < 4; ++c) Pn[q * LN + gj + 16 * c] = mv[KB + 1][c];
+              for (int c = KB + 1; c < 4; ++c) Pn[qn * LN + gj + 16 * c] = mv[KB + 1][c];
             }
           }
         }
@@ -323,62 +339,89 @@ __global__ __launch_bounds__(LT, KC == 32 ? 2 : 1) void local_kernel(LocalArgs a
       if (a.gamma) a.gamma[p + (int64_t)t * a.n_prob] = d;
       if (!(d > 0.0) || !__builtin_isfinite(d)) atomicOr(a.status, kStatusNotSpd);
     }
-    // 3. y = M^{-1} delta = L^{-T} D^{-1} L^{-1} delta, delta the centred
-    //    ensemble row of the state point, four rows at a time (wave 0, lane i
-    //    holds entry i; L[i][k] = Msh[k][i] / d_k for i > k).
+    // 3. y = M^{-1} delta = L^{-T} D^{-1} z with z = L^{-1} delta from the
+    //    factorization, four rows at a time (wave 0, lane i holds entry i;
+    //    L[i][k] = Msh[k][i] / d_k for i > k).
     if (w == 0) {
-      const double x = (double)xbuf[l];
-      const double mean = wsum(x) / (double)a.N;
-      double z = (l < a.N) ? x - mean : 0.0;
-#pragma unroll 2
-      for (int k0 = 0; k0 < LN; k0 += 4) {        // forward: z = L^{-1} delta
-        double zp[4], f[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          double v = rdlane(z, k0 + q);
-#pragma unroll
-          for (int u = 0; u < q; ++u) v -= Msh[(k0 + u) * LDM + k0 + q] * f[u];
-          zp[q] = v;
-          f[q] = v * ipiv[k0 + q];
-        }
-        double acc_z = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc_z += Msh[(k0 + q) * LDM + l] * f[q];
-        const int dq = l - k0;
-        const double zin = dq == 0 ? zp[0] : dq == 1 ? zp[1] : dq == 2 ? zp[2] : zp[3];
-        z = (l > k0 + 3) ? z - acc_z : (dq >= 0 ? zin : z);
-      }
-      double y = z * ipiv[l];                     // D^{-1} z, then y = L^{-T} (D^{-1} z)
+      double y = zf[l] * ipiv[l];                 // D^{-1} z, then y = L^{-T} (D^{-1} z)
 #pragma unroll 2
       for (int k0 = LN - 4; k0 >= 0; k0 -= 4) {
         double yp[4];
 #pragma unroll
-        for (int q = 3; q >= 0; --q) {
-          double v = rdlane(y, k0 + q);
+        for (int qq = 3; qq >= 0; --qq) {
+          double v = rdlane(y, k0 + qq);
 #pragma unroll
-          for (int u = q + 1; u < 4; ++u) v -= Msh[(k0 + q) * LDM + k0 + u] * ipiv[k0 + q] * yp[u];
-          yp[q] = v;
+          for (int u = qq + 1; u < 4; ++u) v -= Msh[(k0 + qq) * LDM + k0 + u] * ipiv[k0 + qq] * yp[u];
+          yp[qq] = v;
         }
         double acc_y = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc_y += Msh[l * LDM + k0 + q] * yp[q];
+        for (int qq = 0; qq < 4; ++qq) acc_y += Msh[l * LDM + k0 + qq] * yp[qq];
         const int dq = l - k0;
         const double yin = dq == 0 ? yp[0] : dq == 1 ? yp[1] : dq == 2 ? yp[2] : yp[3];
         y = (l < k0) ? y - acc_y * ipiv[l] : (dq <= 3 ? yin : y);
       }
-      yv[l] = y;
+      yv[l] = (l < a.N) ? y : 0.0;
     }
-    __syncthreads();
-    // 4. xa = x^B_s + (y^T B) / sqrt(N-1): each wave sums a quarter of the rows
-    {
-      double part = 0.0;
+    // 4. V_p^T Z_p = M^{-1} (R^{-1} V_p)^T D_p (the Woodbury form of eq. SWM
+    //    with one panel), so the centre-point update of the SMEnKF
+    //    (Section 3.1) is xa = x^B_s + (R^{-1} V_p y)^T D_p / sqrt(N-1): a
+    //    second pass over the window, 64 rows a stage, lane = row and wave w
+    //    = members w, w + 4, ...: s_i = (V_i . y) / r_i from the four waves'
+    //    partial dots, then every lane accumulates s_i D_i over its members
+    //    (FP64 arithmetic on the FP32 rows); one transposition through the
+    //    LDS sums the lanes at the end.
+    float v4[PER4], d4[PER4];
+    double r4;
+    auto fetch4 = [&](int64_t i0) {
+      const int64_t g = row_of(i0 + l);
+      r4 = a.r[g];
 #pragma unroll
-      for (int i = 16 * w; i < 16 * w + 16; ++i) part += yv[i] * Bsh[i * LDM + l];
-      ypart[w * LN + l] = part;
+      for (int j = 0; j < PER4; ++j) {
+        v4[j] = ld(a.V, g, w + 4 * j, O32 ? coff4[j] : 0u);
+        d4[j] = ld(a.D, g, w + 4 * j, O32 ? coff4[j] : 0u);
+      }
+    };
+    fetch4(0);
+    __syncthreads();                               // y is complete; the LDS is free
+    double yr[PER4], o4[PER4];
+#pragma unroll
+    for (int j = 0; j < PER4; ++j) {
+      yr[j] = yv[w + 4 * j];
+      o4[j] = 0.0;
+    }
+    int buf = 0;
+    for (int64_t i0 = 0; i0 < m; i0 += K4) {
+      const bool row_ok = i0 + l < m;
+      double wp = 0.0;                             // members past N: y = 0
+#pragma unroll
+      for (int j = 0; j < PER4; ++j) wp += (double)v4[j] * yr[j];
+      wpart[(buf * 4 + w) * K4 + l] = wp;
+      float dn[PER4];
+#pragma unroll
+      for (int j = 0; j < PER4; ++j) dn[j] = d4[j];
+      const double rinv = row_ok ? 1.0 / r4 : 0.0;
+      fetch4(i0 + K4);                             // past the window: clamped rows, unused
+      __syncthreads();
+      const double* wb = wpart + buf * 4 * K4;
+      const double sr = ((wb[l] + wb[K4 + l]) + (wb[2 * K4 + l] + wb[3 * K4 + l])) * rinv;
+#pragma unroll
+      for (int j = 0; j < PER4; ++j) o4[j] += sr * (double)dn[j];
+      buf ^= 1;
+    }
+    __syncthreads();                               // the last partials are read
+#pragma unroll
+    for (int j = 0; j < PER4; ++j) ored[(w + 4 * j) * LD4D + l] = o4[j];
+    __syncthreads();
+    {
+      double part = 0.0;                           // member l, lanes 16w .. 16w+15
+#pragma unroll
+      for (int i = 16 * w; i < 16 * w + 16; ++i) part += ored[l * LD4D + i];
+      opart[w * LN + l] = part;
     }
     __syncthreads();
     if (w == 0 && l < a.N) {
-      const double part = (ypart[l] + ypart[LN + l]) + (ypart[2 * LN + l] + ypart[3 * LN + l]);
+      const double part = (opart[l] + opart[LN + l]) + (opart[2 * LN + l] + opart[3 * LN + l]);
       a.XA[p + (int64_t)l * a.ldxa] = (float)((double)xbuf[l] + part * a.inv_sqrt);
     }
   }
