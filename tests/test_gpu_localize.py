@@ -70,15 +70,22 @@ def test_localized_without_taper_is_the_analysis():
     _gate(XA, oracle.analysis(XB, V, Z), XB, 1e-12)
 
 
-def test_localized_fp32():
+@pytest.mark.parametrize("n_state,N,stride,radius", [
+    (1024, 48, 2, -1),     # members padded to 64 (resident S tile)
+    (257, 64, 3, 40),      # ragged row tile and observation step, radius
+    (300, 96, 2, -1),      # N > 64: the general kernel
+])
+def test_localized_fp32(n_state, N, stride, radius):
     import torch
+    print(f"localize fp32 n_state={n_state} N={N} stride={stride}", flush=True)
     pk = _pk()
-    XB, V, Z, loc, r = _inputs(1024, 48, 2, seed=5)
+    XB, V, Z, loc, r = _inputs(n_state, N, stride, seed=5 + N)
     f = lambda a: a.astype(np.float32).astype(np.float64)
     plan = pk.Plan(dev(r), dev(V, torch.float32))
-    XA = plan.localized_analysis(dev(XB, torch.float32), dev(Z, torch.float32), dev(loc), 1024.0, -1, 1024)
+    L = float(n_state)
+    XA = plan.localized_analysis(dev(XB, torch.float32), dev(Z, torch.float32), dev(loc), L, radius, n_state)
     torch.cuda.synchronize()
-    ref = oracle.localized_analysis(f(XB), f(V), f(Z), loc, 1024.0, -1, 1024)
+    ref = oracle.localized_analysis(f(XB), f(V), f(Z), loc, L, radius, n_state)
     _gate(host(XA), ref, f(XB), 2e-5)
 
 
