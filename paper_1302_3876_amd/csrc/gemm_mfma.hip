@@ -429,6 +429,145 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------- analysis, small N
+// X^A = X^B + (X^B - xbar 1^T) B for N = K = m <= 16 NT16 (NT16 even, so
+// NP = 16 NT16 = nn_bt_rows(N)). Persistent blocks walk row tiles of 64
+// rows; the block keeps all of B (NP x NP, from Bt) in the LDS and reads
+// each X^B row tile from HBM once: the tile is staged in the LDS (it is the
+// left factor, its row means and the epilogue's X^B); the block's next two
+// tiles are in flight in registers while the matrix cores work.
+// 8 waves: wave w forms the output rows 16 (w % 4) .. for half of the
+// column tiles.
+constexpr int AS_TR = 64;
+
+constexpr int AS_NT = 512;                        // 8 waves: two per SIMD
+
+template <typename T, int NT16>
+__global__ __launch_bounds__(AS_NT) void analysis_small_kernel(NnArgs p, const T* __restrict__ Bt, int ldbc) {
+  typedef typename MfOf<T>::type MF;
+  constexpr int NP = 16 * NT16;
+  constexpr int LDB = NP + 4;                     // Bs[k][col]
+  constexpr int LDX = AS_TR + 4;                  // Xs[col][row]
+  constexpr int QS = AS_NT / AS_TR;               // threads per row when staging (8)
+  constexpr int PX = NP / QS;                     // staged tile elements per thread
+  constexpr int HC = NT16 / 2;                    // column tiles per wave
+  __shared__ T Bs[NP * LDB];
+  __shared__ T Xs[NP * LDX];
+  __shared__ double part[QS][AS_TR];
+  const T* __restrict__ X = static_cast<const T*>(p.A);
+  T* __restrict__ XA = static_cast<T*>(p.Cout);
+  const int t = threadIdx.x, l = t % kWave, w = t / kWave;
+  const int N = p.K;
+  const int64_t n = p.n;
+  const int64_t tiles = (n + AS_TR - 1) / AS_TR;
+  for (int e = t; e < NP * NP; e += AS_NT) {       // B: rows and columns past N are zero in Bt
+    const int k = e / NP, c = e % NP;
+    Bs[k * LDB + c] = Bt[(int64_t)k * ldbc + c];
+  }
+  // staged element q of this thread: row t % 64, column t / 64 + 8 q
+  const int xr = t % AS_TR, xc = t / AS_TR;
+  // wave w: output rows 16 (w % 4) .., column tiles (w / 4) HC ..
+  const int ro = 16 * (w % 4) + l % 16;
+  const int ct0 = (w / 4) * HC;
+  auto fetch = [&](T (&xreg)[PX], int64_t tile) {
+    const int64_t row = min(tile * AS_TR + xr, n - 1);
+#pragma unroll
+    for (int q = 0; q < PX; ++q) xreg[q] = X[row + (int64_t)min(xc + QS * q, N - 1) * p.lda];
+  };
+  // one row tile from the registers xreg, which then load the tile two
+  // steps ahead
+  auto process = [&](T (&xreg)[PX], int64_t tile) {
+    __syncthreads();                               // the previous tile's epilogue is done with Xs
+    {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < PX; ++q) {
+        const int c = xc + QS * q;
+        const T v = c < N ? xreg[q] : T(0);
+        Xs[c * LDX + xr] = v;
+        s += (double)v;
+      }
+      part[xc][xr] = s;
+    }
+    __syncthreads();
+    if (tile + 2 * (int64_t)gridDim.x < tiles) fetch(xreg, tile + 2 * (int64_t)gridDim.x);
+    __builtin_amdgcn_sched_barrier(0);
+    double msum = 0.0;
+#pragma unroll
+    for (int z = 0; z < QS; ++z) msum += part[z][ro];
+    const double mean = msum / (double)N;
+    typename MF::acc_t acc[HC];
+#pragma unroll
+    for (int i = 0; i < HC; ++i) acc[i] = MF::zero();
+    // rows k >= N of Bs are zero, so the left factor needs no mask there
+#pragma unroll 8
+    for (int k = 0; k < NP; k += MF::KSTEP) {
+      const int kk = k + l / 16;
+      const T aop = (T)((double)Xs[kk * LDX + ro] - mean);
+#pragma unroll
+      for (int i = 0; i < HC; ++i) acc[i] = MF::mma(Bs[kk * LDB + 16 * (ct0 + i) + l % 16], aop, acc[i]);
+    }
+    const int64_t row = tile * AS_TR + ro;
+#pragma unroll
+    for (int i = 0; i < HC; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = 16 * (ct0 + i) + MF::row(l, r);
+        const double out = (double)Xs[min(col, NP - 1) * LDX + ro] + (double)acc[i][r];
+        if (col < N && row < n) XA[row + (int64_t)col * p.ldo] = (T)out;
+      }
+  };
+  T xa[PX], xb[PX];
+  const int64_t G = gridDim.x;
+  if ((int64_t)blockIdx.x < tiles) fetch(xa, blockIdx.x);
+  if ((int64_t)blockIdx.x + G < tiles) fetch(xb, blockIdx.x + G);
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += 2 * G) {
+    process(xa, tile);
+    if (tile + G < tiles) process(xb, tile + G);
+  }
+}
+
+template <typename T, int NT16>
+enkf_status analysis_small_go(NnArgs p, const T* Bt, int ldbc, hipStream_t s) {
+  static int occ = 0, cus = 0;                    // resident blocks per CU and CUs, found once
+  if (occ == 0) {
+    int b = 0, dev = 0, c = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, analysis_small_kernel<T, NT16>, AS_NT, 0) != hipSuccess ||
+        b < 1)
+      b = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+      c = 256;
+    cus = c;
+    occ = b;
+  }
+  const int64_t tiles = (p.n + AS_TR - 1) / AS_TR;
+  const int64_t blocks = std::min<int64_t>(tiles, (int64_t)cus * occ);
+  analysis_small_kernel<T, NT16><<<(unsigned)blocks, AS_NT, 0, s>>>(p, Bt, ldbc);
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
+// N (= K = m) for which the small-N analysis kernel applies: its LDS holds
+// B and one row tile.
+template <typename T>
+bool analysis_small_fits(int N) {
+  return N >= 2 && N <= (sizeof(T) == 8 ? 96 : 128);
+}
+
+template <typename T>
+enkf_status analysis_small(NnArgs p, const T* Bt, int ldbc, hipStream_t s) {
+  const int nt16 = 2 * ((p.K + 31) / 32);
+  switch (nt16) {
+    case 2: return analysis_small_go<T, 2>(p, Bt, ldbc, s);
+    case 4: return analysis_small_go<T, 4>(p, Bt, ldbc, s);
+    case 6: return analysis_small_go<T, 6>(p, Bt, ldbc, s);
+    default:
+      if constexpr (sizeof(T) == 4) return analysis_small_go<T, 8>(p, Bt, ldbc, s);
+      return fail(ENKF_ERR_NOT_SUPPORTED, "analysis: ensemble too large for the small-N kernel");
+  }
+}
+
 constexpr int64_t kTnTargetBlocks = 768;   // ~3 blocks per CU
 constexpr int64_t kTnMinRows = 1024;
 
@@ -531,7 +670,11 @@ enkf_status nn_typed(int mode, NnArgs p, hipStream_t s) {
   ENKF_HIP_CHECK(hipGetLastError());
   const bool vec = aligned16(p.A, p.lda, sizeof(T)) && p.n % (int64_t)(16 / sizeof(T)) == 0;
   if (mode == NN_UPDATE) return nn_pick<T, NN_UPDATE>(p, Bt, ldbc, vec, s);
-  if (mode == NN_ANALYSIS) return nn_pick<T, NN_ANALYSIS>(p, Bt, ldbc, vec, s);
+  if (mode == NN_ANALYSIS) {
+    if (p.K == p.m && p.Cin == p.A && p.ldc == p.lda && analysis_small_fits<T>(p.K))
+      return analysis_small<T>(p, Bt, ldbc, s);
+    return nn_pick<T, NN_ANALYSIS>(p, Bt, ldbc, vec, s);
+  }
   return nn_pick<T, NN_RESIDUAL>(p, Bt, ldbc, vec, s);
 }
 

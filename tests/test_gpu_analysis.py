@@ -1,0 +1,78 @@
+"""The analysis update X^A = X^B + S V^T Z (Section 3.1, the SMEnKF update)
+through the C ABI, against the FP64 oracle, over ensemble sizes that take
+each of the analysis kernels: the small-N kernel (N <= 96 in FP64, <= 128
+in FP32; member padding to 32, 64, 96 and 128) and the general tiled kernel
+beyond, with row counts that leave a ragged last row tile.
+
+Tolerances: FP64 — the increment is a sum of N products of FP64 values
+whose order differs from the oracle's, so every element of it agrees to a
+few units of roundoff of the largest increment (1e-11 of it). FP32 storage
+and FP32 matrix cores — 2e-5 of the largest increment (the FP32 rounding of
+X^B, G and the products, summed over N <= 160 terms)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _pk():
+    import paper_1302_3876_amd as pk
+    return pk
+
+
+def _inputs(n_state, n_obs, N, seed):
+    g = np.random.default_rng(seed)
+    XB = 1.7 + 2.9 * g.standard_normal((n_state, N))
+    V = g.standard_normal((n_obs, N)) / np.sqrt(N - 1)
+    Z = g.standard_normal((n_obs, N))
+    r = g.uniform(0.5, 1.5, n_obs)
+    return XB, V, Z, r
+
+
+def _check(XA, XB, ref, tol):
+    inc, inco = XA - XB, ref - XB
+    err = np.max(np.abs(inc - inco))
+    assert err <= tol * np.max(np.abs(inco)), (err, np.max(np.abs(inco)))
+
+
+@pytest.mark.parametrize("n_state,N", [(1000, 2), (777, 33), (4096, 64), (300, 65), (2113, 96), (513, 97), (200, 160)])
+def test_analysis_fp64(n_state, N):
+    import torch
+    print(f"analysis fp64 n_state={n_state} N={N}", flush=True)
+    pk = _pk()
+    XB, V, Z, r = _inputs(n_state, 257, N, seed=n_state + N)
+    plan = pk.Plan(dev(r), dev(V))
+    XA = host(plan.analysis(dev(XB), dev(Z)))
+    torch.cuda.synchronize()
+    _check(XA, XB, oracle.analysis(XB, V, Z), 1e-11)
+
+
+@pytest.mark.parametrize("n_state,N", [(1000, 20), (640, 64), (2113, 96), (1029, 128), (300, 129)])
+def test_analysis_fp32_storage(n_state, N):
+    import torch
+    print(f"analysis fp32 n_state={n_state} N={N}", flush=True)
+    pk = _pk()
+    XB, V, Z, r = _inputs(n_state, 193, N, seed=7 * N + n_state)
+    XB32 = XB.astype(np.float32).astype(np.float64)
+    plan = pk.Plan(dev(r), dev(V))
+    XA = host(plan.analysis_ex(dev(XB32, torch.float32), dev(Z), math="f32"))
+    torch.cuda.synchronize()
+    _check(XA, XB32, oracle.analysis(XB32, V, Z), 2e-5)
+
+
+def test_analysis_in_place_output_and_reuse():
+    """A second call on other data gives that data's update (the persistent
+    kernel keeps no state between calls)."""
+    import torch
+    pk = _pk()
+    XB, V, Z, r = _inputs(1500, 129, 96, seed=3)
+    plan = pk.Plan(dev(r), dev(V))
+    XA1 = host(plan.analysis(dev(XB), dev(Z)))
+    XB2 = XB[::-1].copy()
+    XA2 = host(plan.analysis(dev(XB2), dev(Z)))
+    torch.cuda.synchronize()
+    _check(XA1, XB, oracle.analysis(XB, V, Z), 1e-11)
+    _check(XA2, XB2, oracle.analysis(XB2, V, Z), 1e-11)
