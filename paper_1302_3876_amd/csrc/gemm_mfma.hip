@@ -77,10 +77,13 @@ __device__ __forceinline__ typename V16<T>::type zero_past(typename V16<T>::type
 
 // ---------------------------------------------------------------- tn
 // Stage layout: S[col][k], col in [0, TA + TILE) (A columns then B columns),
-// k in [0, KC), row stride LDK (FP32: KC+4, 16-byte rows, conflict-free MFMA
-// reads; FP64: KC+1). One LDS buffer: the next stage is prefetched into
-// registers while the matrix cores work on the current one.
-template <typename T> constexpr int tn_ldk() { return sizeof(T) == 8 ? kc_of<T>() + 1 : kc_of<T>() + 4; }
+// k in [0, KC), row stride LDK (KC+4 / KC+2: 16-byte rows). One LDS buffer:
+// the next stage is prefetched into registers while the matrix cores work on
+// the current one. The inner dimension is taken in groups of 4 RV rows (RV =
+// 2): lane group g = l/16 supplies rows RV g .. RV g + RV-1 of the group to
+// RV consecutive MFMAs, read with one LDS load (the sum over the group is the
+// same in any order of its rows).
+template <typename T> constexpr int tn_ldk() { return sizeof(T) == 8 ? kc_of<T>() + 2 : kc_of<T>() + 4; }
 
 // 2 x WA waves, wave tile 64 (m) x 32 (a) = 4 x 2 MFMA tiles; block tile
 // 128 (m) x TA = 32*WA (a). FP64: WA = 4 (two 8-wave blocks per CU); FP32:
@@ -98,6 +101,8 @@ __global__ __launch_bounds__(128 * WA, WA == 2 ? 3 : 4) void tn_partial_kernel(i
   constexpr int W = V16<T>::W;
   constexpr int KC = kc_of<T>();
   constexpr int LDK = tn_ldk<T>();
+  constexpr int RV = 2;                           // inner-dimension rows per operand read
+  typedef T rvt __attribute__((ext_vector_type(RV)));
   constexpr int TN_NT = 128 * WA;
   constexpr int TA = 32 * WA;
   constexpr int COLS = TA + TILE;
@@ -182,16 +187,20 @@ __global__ __launch_bounds__(128 * WA, WA == 2 ? 3 : 4) void tn_partial_kernel(i
     const T* Sa = &S[0];
     const T* Sb = &S[TA * LDK];
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += MF::KSTEP) {
-      T bop[4], aop[2];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) bop[i] = Sb[(m_off + 16 * i + l % 16) * LDK + kk + l / 16];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) aop[j] = Sa[(a_off + 16 * j + l % 16) * LDK + kk + l / 16];
+    for (int kk = 0; kk < KC; kk += 4 * RV) {
+      rvt bq[4], aq[2];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
+        bq[i] = *reinterpret_cast<const rvt*>(&Sb[(m_off + 16 * i + l % 16) * LDK + kk + RV * (l / 16)]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = MF::mma(bop[i], aop[j], acc[i][j]);
+      for (int j = 0; j < 2; ++j)
+        aq[j] = *reinterpret_cast<const rvt*>(&Sa[(a_off + 16 * j + l % 16) * LDK + kk + RV * (l / 16)]);
+#pragma unroll
+      for (int e = 0; e < RV; ++e)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = MF::mma(bq[i][e], aq[j][e], acc[i][j]);
     }
     if (kWide && ++stage == kFlush) {
       flush();
