@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--block", type=int, default=0, help="panel width of the blocked forms (0: automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
+    ap.add_argument("--calibrate-mfma", action="store_true",
+                    help="print the measured matrix-core throughput (enkf_mfma_peak) per input type and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 4 times (the known-size kernel that scales the HBM "
                          "byte counters) and exit")
@@ -483,6 +485,42 @@ def run_c5(w, args, pk, torch):
     return res
 
 
+def copy_ms(torch, nbytes):
+    """Average time of a plain device copy of nbytes (4 timed after 4 warm-up)."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(4):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 4
+    del src, dst
+    return ms
+
+
+def add_measured_peak(roof, dtype, pk, torch):
+    """Beside the published peak: the same figure measured on this device (a
+    1 GiB device copy for HBM-bound kernels, the MFMA loop of enkf_mfma_peak
+    for matrix-core-bound ones) and the kernel's fraction of it."""
+    if not isinstance(roof, dict):
+        return
+    if roof.get("unit") == "GB/s":
+        nbytes = 1 << 30
+        peak = 2 * nbytes / copy_ms(torch, nbytes) / 1e6
+        src = "1 GiB device copy, read + write bytes"
+    else:
+        peak = pk.mfma_peak(dtype)
+        src = f"enkf_mfma_peak({dtype})"
+    roof["measured_peak"] = round(peak, 1)
+    roof["measured_peak_source"] = src
+    roof["measured_frac"] = round(roof["achieved"] / peak, 4) if roof.get("achieved") else None
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -493,21 +531,15 @@ def main():
 
     if args.calibrate_copy > 0:
         nbytes = args.calibrate_copy << 20
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(4):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(4):
-            dst.copy_(src)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / 4
+        ms = copy_ms(torch, nbytes)
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "launches": 8,
                           "copy_ms": round(ms, 4), "copy_GBps_read_plus_write": round(2 * nbytes / ms / 1e6, 1)}),
               flush=True)
+        return
+    if args.calibrate_mfma:
+        import paper_1302_3876_amd as pk
+        print(json.dumps({"mfma_TFLOPs_measured": {m: round(pk.mfma_peak(m), 1) for m in ("f64", "f32", "bf16", "f16")},
+                          "mfma_TFLOPs_published": MFMA_PEAK_TFLOPS}), flush=True)
         return
 
     import paper_1302_3876_amd as pk
@@ -537,6 +569,7 @@ def main():
                                       f"H=I, R=0.01 I, windows n_p~U{{16..512}}; FP32 storage, FP64 pivots; one "
                                       f"graph-replayed launch", "name": "c4", "tuned": cfg},
                "roofline": roof, "cpu_baseline": base, "max_increment_err_vs_oracle": err}
+        add_measured_peak(out["roofline"], "f32", pk, torch)
         print(json.dumps(out), flush=True)
         return
     if args.workload == "loc":
@@ -571,6 +604,7 @@ def main():
                             "kernel": "localize64_kernel<double> (resident S tile; S V^T tile, impact weights, times Z)",
                             "avg_launch_us": head["avg_launch_us"], "alg_flops_per_launch": head["alg_flops_per_launch"]},
                "cpu_baseline": base, "forms": res}
+        add_measured_peak(out["roofline"], "f64", pk, torch)
         print(json.dumps(out), flush=True)
         return
     if args.workload == "cycle":
@@ -615,6 +649,7 @@ def main():
                             "frac": round(ach / MFMA_PEAK_TFLOPS["f32"], 4) if ach else None, "traffic": None,
                             "kernel": "tn_partial_kernel<float> (panel products)"},
                "cpu_baseline": None, "forms": res}
+        add_measured_peak(out["roofline"], "f32", pk, torch)
         print(json.dumps(out), flush=True)
         return
     w = synth.c2() if args.workload == "c2" else synth.c3()
@@ -657,6 +692,7 @@ def main():
     if "plain_f64" in forms:
         p = forms["plain_f64"]["ms_per_step"]
         out["speedup_vs_plain_f64"] = {k: round(p / v["ms_per_step"], 3) for k, v in forms.items()}
+    add_measured_peak(out["roofline"], {"bf16x3": "bf16", "f16x2": "f16"}.get(primary["math"], primary["math"]), pk, torch)
     print(json.dumps(out), flush=True)
 
 

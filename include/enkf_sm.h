@@ -271,6 +271,18 @@ enkf_status enkf_sm_get_timing(enkf_sm_plan plan, int32_t kernel_class, double* 
 /* Release the workspace. Synchronises the plan's stream first. */
 void enkf_sm_destroy(enkf_sm_plan plan);
 
+/*
+ * Measured matrix-core throughput of the current device, the on-box
+ * counterpart of the published peaks the rooflines divide by (MI355X dense:
+ * FP64 78.6, FP32 157.3, BF16/FP16 2500 TFLOP/s). Runs a kernel in which
+ * every wave issues 4096 x 8 independent MFMAs on register operands
+ * (16x16x4 for F64/F32, 16x16x32 for BF16/F16; no memory traffic) on a
+ * private stream, times it with HIP events and stores TFLOP/s in *tflops.
+ * math: ENKF_MATH_F64, _F32, _BF16 or _F16 (else ENKF_ERR_NOT_SUPPORTED).
+ * Allocates 4 bytes of device memory for the duration of the call.
+ */
+enkf_status enkf_mfma_peak(enkf_math math, double* tflops);
+
 const char* enkf_status_string(enkf_status s);
 /* Detail of the last error raised on the calling thread. */
 const char* enkf_last_error_message(void);

@@ -98,6 +98,8 @@ def lib():
     L.enkf_local_sync.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.enkf_local_destroy.argtypes = [vp]
     L.enkf_local_destroy.restype = None
+    L.enkf_mfma_peak.argtypes = [ctypes.c_int, ctypes.POINTER(dbl)]
+    L.enkf_mfma_peak.restype = ctypes.c_int
     L.enkf_status_string.argtypes = [ctypes.c_int]
     L.enkf_status_string.restype = ctypes.c_char_p
     L.enkf_last_error_message.argtypes = []
@@ -434,6 +436,14 @@ class LocalPlan:
 
 
 # ------------------------------------------------------------------ Lorenz-96 cycling filter
+def mfma_peak(math: str = "f64") -> float:
+    """Measured matrix-core throughput of the current device in TFLOP/s
+    (enkf_mfma_peak); math is "f64", "f32", "bf16" or "f16"."""
+    out = ctypes.c_double(0.0)
+    _check(lib().enkf_mfma_peak(MATH[math], ctypes.byref(out)), "enkf_mfma_peak")
+    return out.value
+
+
 def l96_forecast(X, nsteps: int, F: float = 8.0, dt: float = 0.05):
     """Advance every column of the FP64 device matrix X by nsteps RK4 steps of
     the Lorenz-96 model, in place (enkf_l96_forecast)."""

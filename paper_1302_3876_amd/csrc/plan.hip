@@ -664,7 +664,6 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
 // with rho = D - (R Z + V (V^T Z)) formed in FP64.
 enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync) {
   const int64_t n = desc.n_obs;
-  const int N = desc.n_ens;
   last.refine_iters = 0;
   last.rel_residual = -1.0;
   if (nrhs == 0) return ENKF_SUCCESS;
