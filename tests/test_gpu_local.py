@@ -82,3 +82,33 @@ def test_local_rejects_bad_windows():
         pk.LocalPlan(100, 8, 100, [0], [0], [0])
     with pytest.raises(pk.EnkfError):
         pk.LocalPlan(100, 65, 100, [0], [5], [0])
+
+
+def test_local_leading_dimension_past_4_gib():
+    """V and D with a leading dimension that puts their last member more than
+    4 GiB from the base (the kernel's 64-bit row offsets), then the same plan
+    on compact copies (32-bit offsets, a different kernel in its graph)."""
+    import torch
+    print("local with ldv past 4 GiB", flush=True)
+    n_ens, n_prob = 4, 40
+    w = synth.c4(n_ens=n_ens, n_prob=n_prob, lo=4, hi=60)
+    start, ln, pts = w.extra["win_start"], w.extra["win_len"], w.extra["state_idx"]
+    V32, D32, XB32, Vd, Dd, XBd = _inputs(w)
+    ldv = (1 << 29) + 13                          # (N-1) * ldv * 4 bytes > 4 GiB
+    n = w.n_obs
+    wide = []
+    for M in (V32, D32):
+        buf = torch.empty((n_ens - 1) * ldv + n, dtype=torch.float32, device="cuda")
+        view = buf.as_strided((n, n_ens), (1, ldv))
+        view.copy_(torch.as_tensor(M))
+        wide.append(view)
+    plan = _pk().LocalPlan(w.n_obs, n_ens, w.n_state, start, ln, pts, tune=False)
+    r = dev(w.r)
+    xa_wide = host(plan.analysis(r, wide[0], wide[1], XBd))
+    plan.sync()
+    del wide
+    torch.cuda.empty_cache()
+    xa_compact = host(plan.analysis(r, Vd, Dd, XBd))
+    plan.sync()
+    _check(w, xa_wide, V32, D32, XB32, start, ln, pts, 1e-5)
+    _check(w, xa_compact, V32, D32, XB32, start, ln, pts, 1e-5)
