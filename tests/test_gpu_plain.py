@@ -157,8 +157,11 @@ def test_c1_full_path_fp64():
     w = synth.c1()
     V, D, Z, XA, plan = _full_path(w, None)
     Vo, Do = oracle.build_vd(w.XB, w.obs_idx, w.y, w.E)
-    assert np.allclose(V, Vo, rtol=1e-14, atol=1e-16)
-    assert np.allclose(D, Do, rtol=1e-14, atol=1e-16)
+    # the member mean is a sum of N FP64 terms in an order the definition does
+    # not fix: the two orders differ by at most ~N eps max|X^B|
+    N, eps = w.XB.shape[1], 2.0 ** -52
+    assert np.max(np.abs(V - Vo)) <= 4 * N * eps * np.max(np.abs(w.XB)) / np.sqrt(N - 1)
+    assert np.max(np.abs(D - Do)) <= 4 * eps * (np.max(np.abs(w.y)) + np.max(np.abs(w.E)) + np.max(np.abs(w.XB)))
     Zo = oracle.sm_solve(w.r, Vo, Do)["Z"]
     fp64_gate(w.r, Vo, Do, Z, Zo)
     XAo = oracle.analysis(w.XB, Vo, Zo)
