@@ -6,6 +6,8 @@
 //    (Section 3.3); the kernel leaves M^{-1} for the panel update
 //    X <- X - U_K M^{-1} V_K^T X (eq. SWM with a rank-b term);
 //  - Q = M^{-1} P_X, a b x m product in FP64.
+#include <type_traits>
+
 #include "enkf_internal.h"
 #include "panel.h"
 
@@ -27,18 +29,26 @@ __global__ __launch_bounds__(256) void scale_rows_kernel(int64_t n, int m, const
 
 // One block of 256 threads as a 16 x 16 grid; thread (ti, tj) keeps the
 // elements (i, j) = (ti + 16 r, tj + 16 c), r, c < 8, of the symmetrised
-// M = I + (P_K + P_K^T)/2 in registers. M is inverted in place by b
-// symmetric sweeps (Gauss-Jordan elimination in the natural order, without
-// pivoting, which M being SPD allows): sweep k divides by the current
-// diagonal element k, which is the k-th pivot of M = L D L^T, i.e. the
-// gamma of level k0 + k. After the b sweeps the registers hold -M^{-1}.
-// Only column k is shared per sweep (through LDS, double-buffered: one
-// barrier per sweep).
+// M = I + (P_K + P_K^T)/2 (padded with identity rows to a multiple of 4) in
+// registers. M is inverted in place by block sweeps on four pivots at a time
+// (Gauss-Jordan elimination in the natural order without pivoting, which M
+// being SPD allows; a block sweep on K = {k0..k0+3} equals the four single
+// sweeps): with W = A_KK^{-1},
+//   A_ij -= (A_iK W) A_Kj (i, j outside K),  A_iK <- A_iK W,
+//   A_Kj <- W A_Kj,  A_KK <- -W.
+// Every element takes the uniform update A_ij -= (A_iK W) . A_jK; the threads
+// holding K rows or columns then set those to their swept values. The pivots
+// of A_KK = L4 D4 L4^T are those of M = L D L^T, the gamma of levels
+// k0..k0+3 (Section 3.3). After all sweeps the registers hold -M^{-1}. The
+// next four columns are published through the LDS (double-buffered: one
+// barrier per four levels).
 __global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* __restrict__ P, int64_t ldp,
                                                            double* __restrict__ gamma_out, double* __restrict__ Minv,
                                                            unsigned* status) {
-  __shared__ double col[2][kMaxPanel];
+  constexpr int MP = kMaxPanel;
+  __shared__ double pan[2][4 * MP];
   const int t = threadIdx.x, ti = t % 16, tj = t / 16;
+  const int b4 = (b + 3) / 4 * 4;
   double a[8][8];
 #pragma unroll
   for (int r = 0; r < 8; ++r)
@@ -47,43 +57,144 @@ __global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* 
       const int i = ti + 16 * r, j = tj + 16 * c;
       const int ic = min(i, b - 1), jc = min(j, b - 1);
       const double x = P[ic + (int64_t)jc * ldp], y = P[jc + (int64_t)ic * ldp];
-      a[r][c] = (i < b && j < b) ? (i == j ? 1.0 : 0.0) + 0.5 * (x + y) : 0.0;
+      a[r][c] = (i < b && j < b) ? (i == j ? 1.0 : 0.0) + 0.5 * (x + y) : (i == j && i < b4 ? 1.0 : 0.0);
     }
-  if (tj == 0)
+  if (tj < 4)                                      // columns 0..3
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
-      if (ti + 16 * r < b) col[0][ti + 16 * r] = a[r][0];
+    for (int r = 0; r < 8; ++r) pan[0][tj * MP + ti + 16 * r] = a[r][0];
   __syncthreads();
-  for (int k = 0; k < b; ++k) {
-    const double* __restrict__ ck = col[k & 1];
-    double* __restrict__ cn = col[(k + 1) & 1];
-    const double d = ck[k];
-    if (t == 0) {
-      gamma_out[k] = d;
-      if (!(d > 0.0) || !__builtin_isfinite(d)) atomicOr(status, kStatusNotSpd);
-    }
-    const double inv = 1.0 / d;
-    double ci[8], cj[8];
+  auto phase = [&](auto kb_c) {
+    constexpr int KB = decltype(kb_c)::value;
+    if (16 * KB >= b4) return;
+#pragma unroll 1
+    for (int ss = 0; ss < 4; ++ss) {
+      const int k0 = 16 * KB + 4 * ss;
+      if (k0 >= b4) break;
+      const double* Pc = pan[ss & 1];
+      double* Pn = pan[(ss + 1) & 1];
+      // A_KK = L4 D4 L4^T and W = A_KK^{-1} = L4^{-T} D4^{-1} L4^{-1}
+      double Lm[4][4], dv[4], iv[4];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) ci[r] = ck[min(ti + 16 * r, b - 1)];
+      for (int q = 0; q < 4; ++q) {
+        double e = Pc[q * MP + k0 + q];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) cj[c] = ck[min(tj + 16 * c, b - 1)];
+        for (int u = 0; u < q; ++u) e -= Lm[q][u] * Lm[q][u] * dv[u];
+        dv[q] = e;
+        iv[q] = 1.0 / e;
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
+        for (int v = q + 1; v < 4; ++v) {
+          double f = Pc[q * MP + k0 + v];
+#pragma unroll
+          for (int u = 0; u < q; ++u) f -= Lm[v][u] * Lm[q][u] * dv[u];
+          Lm[v][q] = f * iv[q];
+        }
+      }
+      double Li[4][4];                             // L4^{-1}, unit lower
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (u > q) {
+            Li[q][u] = 0.0;
+          } else if (u == q) {
+            Li[q][u] = 1.0;
+          } else {
+            double x = 0.0;
+#pragma unroll
+            for (int v = u; v < q; ++v) x -= Lm[q][v] * Li[v][u];
+            Li[q][u] = x;
+          }
+        }
+      double W[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double x = 0.0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) x += Li[u][q] * iv[u] * Li[u][v];
+          W[q][v] = x;
+        }
+      if (t == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (k0 + q < b) {
+            gamma_out[k0 + q] = dv[q];
+            if (!(dv[q] > 0.0) || !__builtin_isfinite(dv[q])) atomicOr(status, kStatusNotSpd);
+          }
+      // rows: g_i = A_iK W
+      double g[8][4];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        double x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = Pc[q * MP + ti + 16 * r];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) g[r][v] = fma(x[3], W[3][v], fma(x[2], W[2][v], fma(x[1], W[1][v], x[0] * W[0][v])));
+      }
+      const int pi = ti - k0 % 16, pj = tj - k0 % 16;
+      const bool rowK = pi >= 0 && pi < 4, colK = pj >= 0 && pj < 4;
+      // every element: A_ij -= g_i . A_jK; rows of K: (W A_Kj)_pi
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const int i = ti + 16 * r, j = tj + 16 * c;
-        // by symmetry, element (k, j) of the current matrix is ck[j]
-        const double upd = a[r][c] - ci[r] * cj[c] * inv;
-        double v = upd;
-        if (i == k) v = cj[c] * inv;
-        if (j == k) v = ci[r] * inv;
-        if (i == k && j == k) v = -inv;
-        a[r][c] = v;
-        if (j == k + 1 && i < b) cn[i] = v;
+        double h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h[q] = Pc[q * MP + tj + 16 * c];
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          a[r][c] = fma(-g[r][3], h[3], fma(-g[r][2], h[2], fma(-g[r][1], h[1], fma(-g[r][0], h[0], a[r][c]))));
+        if (rowK) {
+          double x = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (q == pi) x = ((W[q][0] * h[0] + W[q][1] * h[1]) + W[q][2] * h[2]) + W[q][3] * h[3];
+          a[KB][c] = x;
+        }
       }
-    __syncthreads();
-  }
+      if (colK) {                                  // columns of K: (A_iK W)_pj; the K x K block: -W
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          double x = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (q == pj) x = g[r][q];
+          a[r][KB] = x;
+        }
+        if (rowK) {
+          double x = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (q == pi && v == pj) x = -W[q][v];
+          a[KB][KB] = x;
+        }
+      }
+      // the next four columns
+      const int kn = k0 + 4;
+      const int qn = tj - kn % 16;
+      if (kn < b4 && qn >= 0 && qn < 4) {
+        if (ss < 3) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) Pn[qn * MP + ti + 16 * r] = a[r][KB];
+        } else {
+          if constexpr (KB < 7) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) Pn[qn * MP + ti + 16 * r] = a[r][KB + 1];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  };
+  phase(std::integral_constant<int, 0>{});
+  phase(std::integral_constant<int, 1>{});
+  phase(std::integral_constant<int, 2>{});
+  phase(std::integral_constant<int, 3>{});
+  phase(std::integral_constant<int, 4>{});
+  phase(std::integral_constant<int, 5>{});
+  phase(std::integral_constant<int, 6>{});
+  phase(std::integral_constant<int, 7>{});
 #pragma unroll
   for (int r = 0; r < 8; ++r)
 #pragma unroll

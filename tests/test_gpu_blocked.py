@@ -16,7 +16,8 @@ def _pk():
 
 @pytest.mark.parametrize("n,N,b,nrhs", [(64, 1, 1, 1), (1000, 17, 5, 17), (4099, 33, 8, 7), (16384, 96, 32, 96),
                                         (16384, 96, 96, 96), (70001, 40, 40, 40), (3, 50, 16, 50),
-                                        (9000, 130, 64, 130)])
+                                        (9000, 130, 64, 130), (5000, 128, 128, 16), (3001, 127, 127, 5),
+                                        (2000, 101, 101, 9)])
 def test_blocked_fp64_matches_oracle(n, N, b, nrhs):
     import torch
     print(f"blocked fp64 n={n} N={N} b={b} nrhs={nrhs}", flush=True)
