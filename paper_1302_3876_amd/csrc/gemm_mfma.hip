@@ -578,7 +578,7 @@ enkf_status analysis_small(NnArgs p, const T* Bt, int ldbc, hipStream_t s) {
 }
 
 constexpr int64_t kTnTargetBlocks = 768;   // ~3 blocks per CU
-constexpr int64_t kTnMinRows = 1024;
+constexpr int64_t kTnMinRows = 256;
 
 int64_t tn_chunks(int64_t n, int a, int m) {
   const int64_t tiles = (int64_t)((a + TILE - 1) / TILE) * ((m + TILE - 1) / TILE);
