@@ -25,7 +25,8 @@ def _pk():
     return pk
 
 
-@pytest.mark.parametrize("n,m,steps", [(4, 1, 3), (40, 3, 20), (1000, 64, 20), (5000, 5, 10), (8192, 2, 5)])
+@pytest.mark.parametrize("n,m,steps", [(4, 1, 3), (40, 3, 20), (300, 7, 12), (1000, 64, 20), (2000, 9, 8), (4000, 4, 6),
+                                         (5000, 5, 10), (8192, 2, 5)])
 def test_forecast_matches_oracle(n, m, steps):
     import torch
     g = np.random.default_rng(n + m)
