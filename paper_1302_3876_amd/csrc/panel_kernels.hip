@@ -9,6 +9,7 @@
 #include <type_traits>
 
 #include "enkf_internal.h"
+#include "mfma_common.h"
 #include "panel.h"
 
 namespace enkf {
@@ -204,16 +205,37 @@ __global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* 
     }
 }
 
+// Q = M^{-1} P_X on the FP64 matrix cores: block = 64 rows x 32 columns of
+// Q, wave w = rows 16w.. (two 16 x 16 tiles); operands straight from the
+// L2-resident inputs (indices past b or m are clamped; inner indices past b
+// contribute zero).
 __global__ __launch_bounds__(256) void small_gemm_kernel(int b, int m, const double* __restrict__ Minv,
                                                          const double* __restrict__ Pr, int64_t ldp,
                                                          double* __restrict__ Q) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)b * m) return;
-  const int i = (int)(e % b);
-  const int64_t j = e / b;
-  double s = 0.0;
-  for (int k = 0; k < b; ++k) s += Minv[i + (int64_t)k * b] * Pr[k + j * ldp];
-  Q[i + j * b] = s;
+  const int l = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int i0 = blockIdx.x * 64 + 16 * w;
+  const int64_t j0 = (int64_t)blockIdx.y * 32;
+  const int ia = min(i0 + l % 16, b - 1);
+  int64_t jb[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) jb[c] = min(j0 + 16 * c + l % 16, (int64_t)m - 1);
+  mf_d4 acc[2] = {MfmaF64::zero(), MfmaF64::zero()};
+#pragma unroll 4
+  for (int k = 0; k < b; k += 4) {
+    const int kk = k + l / 16;
+    const int kc = min(kk, b - 1);
+    const double a = kk < b ? Minv[ia + (int64_t)kc * b] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[c] = MfmaF64::mma(a, Pr[kc + jb[c] * ldp], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + MfmaF64::row(l, r);
+      const int64_t j = j0 + 16 * c + l % 16;
+      if (i < b && j < m) Q[i + j * b] = acc[c][r];
+    }
 }
 
 // Scale of a residual block: its root mean square (1 when it is zero or
@@ -361,8 +383,9 @@ enkf_status launch_add(int64_t n, int m, const double* X, int64_t ldx, double* Z
 enkf_status launch_small_gemm(int b, int m, const double* Minv, const double* Pr, int64_t ldp, double* Q,
                               hipStream_t s) {
   if (m <= 0) return ENKF_SUCCESS;
-  const int64_t total = (int64_t)b * m;
-  small_gemm_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(b, m, Minv, Pr, ldp, Q);
+  const int64_t ct = ((int64_t)m + 31) / 32;
+  if (ct > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "panel product: too many columns");
+  small_gemm_kernel<<<dim3((unsigned)((b + 63) / 64), (unsigned)ct), 256, 0, s>>>(b, m, Minv, Pr, ldp, Q);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
