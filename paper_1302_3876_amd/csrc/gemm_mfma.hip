@@ -237,9 +237,25 @@ __global__ __launch_bounds__(256) void partial_sum_kernel(int a, int m, int64_t 
   const int64_t am = (int64_t)a * m;
   const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x % 64;
   const int w = threadIdx.x / 64;
+  // wave w sums the chunks w, w + 4, ... into 8 running sums (chunk
+  // w + 4 (8 q + u) goes to sum u), added in order at the end
+  constexpr int U = 8;
+  double su[U] = {};
+  const int64_t ec = e < am ? e : am - 1;
+  int64_t c = w;
+  for (; c + 4 * (U - 1) < chunks; c += 4 * U) {
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = partial[(c + 4 * u) * am + ec];
+#pragma unroll
+    for (int u = 0; u < U; ++u) su[u] += x[u];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (c + 4 * u < chunks) su[u] += partial[(c + 4 * u) * am + ec];
   double s = 0.0;
-  if (e < am)
-    for (int64_t c = w; c < chunks; c += 4) s += partial[c * am + e];
+#pragma unroll
+  for (int u = 0; u < U; ++u) s += su[u];
   red[w][threadIdx.x % 64] = s;
   __syncthreads();
   if (w == 0 && e < am) {
