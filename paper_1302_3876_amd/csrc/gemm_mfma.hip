@@ -22,6 +22,8 @@
 // reads); nn stages A row-contiguous ([k][row]) so its global reads and LDS
 // writes are both along rows. MFMA result lanes run along the output's
 // leading dimension, so stores are coalesced.
+#include <atomic>
+
 #include "enkf_internal.h"
 #include "gemm_mfma.h"
 #include "mfma_common.h"
@@ -554,8 +556,11 @@ __global__ __launch_bounds__(AS_NT) void analysis_small_kernel(NnArgs p, const T
 
 template <typename T, int NT16>
 enkf_status analysis_small_go(NnArgs p, const T* Bt, int ldbc, hipStream_t s) {
-  static int occ = 0, cus = 0;                    // resident blocks per CU and CUs, found once
-  if (occ == 0) {
+  // resident blocks per CU and the CU count, found on the first call (any
+  // thread may find them; they are the same for every device of the part)
+  static std::atomic<int> occ_a{0}, cus_a{0};
+  int occ = occ_a.load(std::memory_order_relaxed), cus = cus_a.load(std::memory_order_relaxed);
+  if (occ == 0 || cus == 0) {
     int b = 0, dev = 0, c = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, analysis_small_kernel<T, NT16>, AS_NT, 0) != hipSuccess ||
         b < 1)
@@ -563,8 +568,10 @@ enkf_status analysis_small_go(NnArgs p, const T* Bt, int ldbc, hipStream_t s) {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
       c = 256;
-    cus = c;
     occ = b;
+    cus = c;
+    occ_a.store(b, std::memory_order_relaxed);
+    cus_a.store(c, std::memory_order_relaxed);
   }
   const int64_t tiles = (p.n + AS_TR - 1) / AS_TR;
   const int64_t blocks = std::min<int64_t>(tiles, (int64_t)cus * occ);

@@ -220,7 +220,6 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(int b, int m, const dou
 #pragma unroll
   for (int c = 0; c < 2; ++c) jb[c] = min(j0 + 16 * c + l % 16, (int64_t)m - 1);
   mf_d4 acc[2] = {MfmaF64::zero(), MfmaF64::zero()};
-#pragma unroll 4
   for (int k = 0; k < b; k += 4) {
     const int kk = k + l / 16;
     const int kc = min(kk, b - 1);
