@@ -60,3 +60,45 @@ def test_c3_full_size(c3, math, rtol):
     print({"rel_residual": rr, "info": info}, flush=True)
     assert rr <= 1e-10
     assert np.allclose(g[:8], _first_gammas(w), rtol=rtol, atol=0)
+
+
+def test_c5_ensemble_shape():
+    """The c5 configuration (N = 1024 members in FP32, panels of 128 levels,
+    FP32 panels refining the FP64 system to 1e-10, the FP32 analysis product
+    with K = N = 1024) on a Lorenz-96 ring of 65,536 variables (n_obs =
+    16,384): build against the oracle, backward error and first pivots of the
+    solve, and the analysis on 256 sampled state rows against the oracle's
+    update of those rows (FP32 storage and products: 2e-5 of the largest
+    increment)."""
+    import torch
+    import paper_1302_3876_amd as pk
+    print("c5 shape, n_state=65536, N=1024", flush=True)
+    w = synth.c5(n_state=65536)
+    XB32 = w.XB.astype(np.float32).astype(np.float64)
+    E32 = w.E.astype(np.float32).astype(np.float64)
+    f32 = torch.float32
+    XBd = pk.to_colmajor(XB32, dtype=f32)
+    n, N = w.n_obs, w.n_ens
+    V32, D32 = pk.colmajor(n, N, f32), pk.colmajor(n, N, f32)
+    pk.enkf_build_vd(XBd, dev(w.obs_idx), dev(w.y), pk.to_colmajor(E32, dtype=f32), V32, D32)
+    Vo, Do = oracle.build_vd(XB32, w.obs_idx, w.y, E32)
+    V, D = host(V32), host(D32)
+    assert np.max(np.abs(V - Vo)) <= 4 * 2.0 ** -24 * np.max(np.abs(Vo)) + 4 * N * 2.0 ** -52 * np.max(np.abs(XB32))
+    assert np.max(np.abs(D - Do)) <= 4 * 2.0 ** -24 * np.max(np.abs(Do))
+    plan = pk.Plan(dev(w.r), dev(V), algo="blocked", math="f32", block=128, refine_max_iter=10, refine_tol=1e-10)
+    Z, info = plan.solve(dev(D), info=True)
+    XA = host(plan.analysis_ex(XBd, Z, math="f32"))
+    torch.cuda.synchronize()
+    g, _ = plan.pivots()
+    Zh = host(Z)
+    plan.close()
+    rho = D - w.r[:, None] * Zh - V @ (V.T @ Zh)
+    rr = float(np.linalg.norm(rho) / np.linalg.norm(D))
+    print({"rel_residual": rr, "info": info}, flush=True)
+    assert rr <= 1e-10
+    g8 = oracle.sm_solve(w.r, np.ascontiguousarray(V[:, :8]), np.ascontiguousarray(D[:, :1]))["gamma"]
+    assert np.allclose(g[:8], g8, rtol=1e-5, atol=0)
+    rows = np.random.default_rng(5).choice(w.n_state, 256, replace=False)
+    ref = oracle.analysis(XB32[rows], V, Zh)
+    inc, inco = XA[rows] - XB32[rows], ref - XB32[rows]
+    assert np.max(np.abs(inc - inco)) <= 2e-5 * np.max(np.abs(inco))
