@@ -98,3 +98,28 @@ def test_localized_bad_arguments():
         with pytest.raises(pk.EnkfError) as e:
             plan.localized_analysis(dev(XB), dev(Z), dev(loc), **kw)
         assert e.value.code == 1
+
+
+@pytest.mark.slow
+def test_localized_full_size_sampled_rows():
+    """The loc workload at full size (Lorenz-96 ring n_state = 32,768, N = 64,
+    n_obs = 16,384, impact exp(-d/n_state) on the ring) in FP64, in the
+    launch bench.py times: three blocks of 64 state rows (the first, one in
+    the middle, the last, i.e. both ends of the ring) against the oracle's
+    rows, same bound as the small cases."""
+    import torch
+    import synth as sy
+    print("localize full size, sampled rows", flush=True)
+    pk = _pk()
+    w = sy.c6()
+    XBd = dev(w.XB)
+    V, D = pk.enkf_build_vd(XBd, dev(w.obs_idx), dev(w.y), dev(w.E))
+    plan = pk.Plan(dev(w.r), V)
+    Z = plan.solve(D)
+    ring = length = w.n_state
+    XA = host(plan.localized_analysis(XBd, Z, dev(w.obs_idx), length, -1, ring))
+    torch.cuda.synchronize()
+    Vh, Zh = host(V), host(Z)
+    for r0 in (0, w.n_state // 2 - 32, w.n_state - 64):
+        ref = oracle.localized_rows(w.XB, Vh, Zh, w.obs_idx, length, -1, ring, r0, r0 + 64)
+        _gate(XA[r0:r0 + 64], ref, w.XB[r0:r0 + 64], 1e-12)
