@@ -9,11 +9,12 @@
 //     registers meanwhile; the FP32 accumulators are emptied into FP64 after
 //     every stage;
 //  2. M = I + A = L D L^T in FP64 registers (upper blocks of a 16 x 16
-//     thread grid, one rank-1 update per level); the pivots D are the
-//     gamma_k of the iterative formula (Section 3.3);
-//  3. y = M^{-1} delta with delta the centred ensemble row of the state
-//     point (one wave, forward and backward substitution four rows at a
-//     time);
+//     thread grid, one rank-4 update per four levels), with the forward
+//     elimination of delta, the centred ensemble row of the state point,
+//     carried along; the pivots D are the gamma_k of the iterative formula
+//     (Section 3.3);
+//  3. y = M^{-1} delta by the backward substitution (one wave, four rows at
+//     a time);
 //  4. since V_p^T Z_p = M^{-1} (R^{-1} V_p)^T D_p (the Woodbury form of
 //     eq. SWM with one panel), the centre-point update (Section 3.1) is
 //     xa = x^B_s + (R^{-1} V_p y)^T D_p / sqrt(N-1), formed by a second,
@@ -22,8 +23,8 @@
 // M and zero products).
 #include <algorithm>
 #include <cmath>
-#include <functional>
 #include <queue>
+#include <type_traits>
 #include <vector>
 
 #include "enkf_internal.h"
