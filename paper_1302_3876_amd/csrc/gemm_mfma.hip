@@ -13,15 +13,18 @@
 //      Bm is FP64 (it comes from the FP64 panel factorisation or from the
 //      FP64 products) and is rounded to the MFMA input type when staged.
 //
-// Both kernels: 256 threads (4 waves, 2 x 2); tn uses 128 x 128 output tiles
-// (each wave 64 x 64 = 4 x 4 MFMA tiles), nn 64 x 128 when the product has at
-// most 128 columns, else 128 x 64 (FP64) or 128 x 128 (FP32); inner-dimension stages of KC staged in LDS
-// through registers with 16-byte global loads, double-buffered so the next
-// stage's loads are in flight while the matrix cores work on the current one.
-// tn stages both operands k-contiguous ([col][k], padded: conflict-free MFMA
-// reads); nn stages A row-contiguous ([k][row]) so its global reads and LDS
+// tn: 2 x WA waves (FP64 8, FP32 4), block tile 128 (m) x 32 WA (a), wave
+// tile 64 x 32. nn: 4 waves (2 x 2), tiles of 64 x 128 when the product has
+// at most 128 columns, else 128 x 64 (FP64) or 128 x 128 (FP32). Both stage
+// the inner dimension in steps of KC through one LDS buffer, the next step
+// loaded into registers (16-byte global loads) while the matrix cores work on
+// the current one. tn stages both operands k-contiguous ([col][k], 16-byte
+// rows); nn stages A row-contiguous ([k][row]) so its global reads and LDS
 // writes are both along rows. MFMA result lanes run along the output's
 // leading dimension, so stores are coalesced.
+//  analysis_small: the ANALYSIS product for N <= 96 (FP64) / 128 (FP32):
+//      persistent 8-wave blocks with the whole right factor in the LDS, each
+//      X^B row tile read once (left factor, row means and epilogue input).
 #include <atomic>
 
 #include "enkf_internal.h"

@@ -1,11 +1,11 @@
 // Small kernels of the blocked solve (gfx950):
 //  - Step 1 as a row scaling, Y = R^{-1} X (eq. SM-step-1);
 //  - the FP64 factorisation of one panel: with P = V_K^T [U_K, X] (b rows),
-//    M = I + V_K^T U_K (symmetrised) is inverted by symmetric sweeps whose
-//    pivots are those of M = L D L^T, the gamma_k of the panel's b levels
-//    (Section 3.3); the kernel leaves M^{-1} for the panel update
+//    M = I + V_K^T U_K (symmetrised) is inverted by symmetric block sweeps
+//    whose pivots are those of M = L D L^T, the gamma_k of the panel's b
+//    levels (Section 3.3); the kernel leaves M^{-1} for the panel update
 //    X <- X - U_K M^{-1} V_K^T X (eq. SWM with a rank-b term);
-//  - Q = M^{-1} P_X, a b x m product in FP64.
+//  - Q = M^{-1} P_X, a b x m product on the FP64 matrix cores.
 #include <type_traits>
 
 #include "enkf_internal.h"
