@@ -28,6 +28,15 @@ __global__ __launch_bounds__(256) void scale_rows_kernel(int64_t n, int m, const
   for (int j = c; j < m; j += gridDim.y) Y[i + (int64_t)j * ldy] = (T)((double)X[i + (int64_t)j * ldx] / rv);
 }
 
+// 1/x to within a few ulp: the hardware estimate refined by two Newton steps
+// (each squares the relative error of the estimate).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
 // One block of 256 threads as a 16 x 16 grid; thread (ti, tj) keeps the
 // elements (i, j) = (ti + 16 r, tj + 16 c), r, c < 8, of the symmetrised
 // M = I + (P_K + P_K^T)/2 (padded with identity rows to a multiple of 4) in
@@ -81,7 +90,7 @@ __global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* 
 #pragma unroll
         for (int u = 0; u < q; ++u) e -= Lm[q][u] * Lm[q][u] * dv[u];
         dv[q] = e;
-        iv[q] = 1.0 / e;
+        iv[q] = recip(e);
 #pragma unroll
         for (int v = q + 1; v < 4; ++v) {
           double f = Pc[q * MP + k0 + v];
