@@ -284,10 +284,11 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
   __shared__ double mean[TR];
   int64_t rt;
   int ct;
-  xcd_tile_map(blockIdx.x, p.n_row_tiles, p.n_col_tiles, &rt, &ct);
+  // with col_loop one block takes every column tile of its row tile (the row
+  // means of ANALYSIS are then formed once per row tile)
+  xcd_tile_map(blockIdx.x, p.n_row_tiles, p.col_loop ? 1 : p.n_col_tiles, &rt, &ct);
   if (rt >= p.n_row_tiles) return;
   const int64_t row0 = rt * TR;
-  const int col0 = ct * TC;
   const float* __restrict__ A = static_cast<const float*>(p.A);
   const int t = threadIdx.x, l = t % kWave, w = t / kWave;
   const int c_off = (w / 2) * (TC / 2), r_off = (w % 2) * (TR / 2);
@@ -318,6 +319,9 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
     }
     __syncthreads();
   }
+  const int ct_end = p.col_loop ? p.n_col_tiles : ct + 1;
+  for (; ct < ct_end; ++ct) {
+  const int col0 = ct * TC;
   mf_f4 acc[CI][RJ], acc2[P::has_scaled ? CI : 1][P::has_scaled ? RJ : 1];
 #pragma unroll
   for (int i = 0; i < CI; ++i)
@@ -439,6 +443,7 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
         if (col < p.m && row < p.n) Cout[row + (int64_t)col * p.ldo] = (float)out;
       }
   }
+  }
 }
 
 template <int MATH>
@@ -452,8 +457,11 @@ template <int MATH, int MODE, int TR, int TC>
 void nn_go(NnArgs p, const typename Lp<MATH>::e_t* Bp, int ldk, int64_t stride, bool vec, hipStream_t s) {
   p.n_row_tiles = (p.n + TR - 1) / TR;
   p.n_col_tiles = (p.m + TC - 1) / TC;
+  // ANALYSIS with several column tiles and rows enough to fill the part: one
+  // block per row tile walks its column tiles (row means formed once)
+  p.col_loop = (MODE == NN_ANALYSIS && p.n_col_tiles > 1 && p.n_row_tiles >= 2048) ? 1 : 0;
   const int64_t groups = (p.n_row_tiles + 7) / 8;
-  const unsigned g = (unsigned)(groups * 8 * p.n_col_tiles);
+  const unsigned g = (unsigned)(groups * 8 * (p.col_loop ? 1 : p.n_col_tiles));
   if (vec) nn_lowp_kernel<MATH, MODE, TR, TC, true><<<g, NT, 0, s>>>(p, Bp, ldk, stride);
   else nn_lowp_kernel<MATH, MODE, TR, TC, false><<<g, NT, 0, s>>>(p, Bp, ldk, stride);
 }

@@ -309,10 +309,11 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
   __shared__ double mean[TR];
   int64_t rt;
   int ct;
-  xcd_tile_map(blockIdx.x, p.n_row_tiles, p.n_col_tiles, &rt, &ct);
+  // with col_loop one block takes every column tile of its row tile (the row
+  // means of ANALYSIS are then formed once per row tile)
+  xcd_tile_map(blockIdx.x, p.n_row_tiles, p.col_loop ? 1 : p.n_col_tiles, &rt, &ct);
   if (rt >= p.n_row_tiles) return;
   const int64_t row0 = rt * TR;
-  const int col0 = ct * TC;
   const T* __restrict__ A = static_cast<const T*>(p.A);
   const int t = threadIdx.x, l = t % kWave, w = t / kWave;
   const int c_off = (w / 2) * (TC / 2), r_off = (w % 2) * (TR / 2);
@@ -349,6 +350,9 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
     __syncthreads();
   }
 
+  const int ct_end = p.col_loop ? p.n_col_tiles : ct + 1;
+  for (; ct < ct_end; ++ct) {
+  const int col0 = ct * TC;
   typename MF::acc_t acc[CI][RJ];
 #pragma unroll
   for (int i = 0; i < CI; ++i)
@@ -456,6 +460,7 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
         else out = (double)din[j][r] - (rr[j] * c + prod);
         if (col < p.m && row < p.n) Cout[row + (int64_t)col * p.ldo] = (T)out;
       }
+  }
   }
 }
 
@@ -666,6 +671,8 @@ enkf_status launch_partial_sum(int a, int m, int64_t chunks, const double* parti
   return ENKF_SUCCESS;
 }
 
+constexpr int64_t kNnLoopRowTiles = 2048;   // ~8 row tiles per CU
+
 // rows: a multiple of the largest stage depth (32); columns: of the widest tile (128)
 int nn_bt_rows(int K) { return (K + 31) / 32 * 32; }
 int nn_bt_cols(int m) { return (m + 127) / 128 * 128; }
@@ -678,8 +685,11 @@ template <typename T, int MODE, int TR, int TC>
 enkf_status nn_go(NnArgs p, const T* Bt, int ldbc, bool vec, hipStream_t s) {
   p.n_row_tiles = (p.n + TR - 1) / TR;
   p.n_col_tiles = (p.m + TC - 1) / TC;
+  // ANALYSIS with several column tiles and rows enough to fill the part: one
+  // block per row tile walks its column tiles (row means formed once)
+  p.col_loop = (MODE == NN_ANALYSIS && p.n_col_tiles > 1 && p.n_row_tiles >= kNnLoopRowTiles) ? 1 : 0;
   const int64_t groups = (p.n_row_tiles + 7) / 8;
-  const int64_t blocks = groups * 8 * p.n_col_tiles;
+  const int64_t blocks = groups * 8 * (p.col_loop ? 1 : p.n_col_tiles);
   if (blocks > 0x7fffffff) return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
   if (vec) nn_kernel<T, MODE, TR, TC, true><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
   else nn_kernel<T, MODE, TR, TC, false><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);

@@ -76,3 +76,27 @@ def test_analysis_in_place_output_and_reuse():
     torch.cuda.synchronize()
     _check(XA1, XB, oracle.analysis(XB, V, Z), 1e-11)
     _check(XA2, XB2, oracle.analysis(XB2, V, Z), 1e-11)
+
+
+@pytest.mark.parametrize("prec,math,N,tol", [("f64", "f64", 160, 1e-11), ("f32", "f32", 256, 2e-5),
+                                             ("f32", "bf16x3", 256, 2e-5)])
+def test_analysis_many_row_tiles(prec, math, N, tol):
+    """Enough rows (more than 2048 row tiles) that one block walks all column
+    tiles of its row tile; 512 sampled rows against the oracle's update of
+    those rows."""
+    import torch
+    print(f"analysis many row tiles {prec}/{math} N={N}", flush=True)
+    pk = _pk()
+    n_state = 2048 * 128 + 77
+    XB, V, Z, r = _inputs(n_state, 301, N, seed=N + 11)
+    if prec == "f32":
+        XB = XB.astype(np.float32).astype(np.float64)
+    plan = pk.Plan(dev(r), dev(V))
+    if prec == "f64":
+        XA = host(plan.analysis(dev(XB), dev(Z)))
+    else:
+        XA = host(plan.analysis_ex(dev(XB, torch.float32), dev(Z), math=math))
+    torch.cuda.synchronize()
+    rows = np.concatenate([np.arange(64), np.random.default_rng(N).choice(n_state, 384, replace=False),
+                           np.arange(n_state - 64, n_state)])
+    _check(XA[rows], XB[rows], oracle.analysis(XB[rows], V, Z), tol)
