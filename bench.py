@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--forms", default="", help="comma list; default: every form of the workload")
     ap.add_argument("--block", type=int, default=0, help="panel width of the blocked forms (0: automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cycle-shapes", action="store_true", help="cycle workload: skip the shape sweep")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
     ap.add_argument("--calibrate-mfma", action="store_true",
                     help="print the measured matrix-core throughput (enkf_mfma_peak) per input type and exit")
@@ -358,6 +359,10 @@ def run_loc(w, args, pk, torch):
 
 
 CYCLE = {"n_state": 1000, "n_ens": 1000, "cycles": 10, "nsteps": 20, "seed": 20130219}
+# (n_state = n_obs, N) across the paper's Lorenz-96 range, timed beside the
+# main configuration: a few cycles each, the first one untimed.
+CYCLE_SHAPES = [(500, 200), (2000, 800), (5000, 1600)]
+CYCLE_SHAPE_CYCLES = 3
 
 
 def run_cycle(args, pk, torch):
@@ -396,7 +401,48 @@ def run_cycle(args, pk, torch):
                                 "rmse_forecast": rmse_f, "rmse_analysis": rmse_a}
         print(f"[bench] cycle {algo}: {np.mean(steady):.3f} ms/cycle, RMSE a {rmse_a[-1]:.5f}", file=sys.stderr,
               flush=True)
+    if not args.no_cycle_shapes:
+        out["cycle_shapes"] = run_cycle_shapes(pk, torch)
     return out, (XB0, obs, r, truths, ys, Es)
+
+
+def run_cycle_shapes(pk, torch):
+    """The cycling filter at other (n_state = n_obs, N) shapes of the paper's
+    Lorenz-96 range, plain and blocked: milliseconds per cycle over all but the
+    first cycle, and the last forecast and analysis RMSE against the truth.
+    With N < n_state and no localization the ensemble spans only part of the
+    state, so the analysis lowers the error without removing it; the two
+    solves agree to roundoff."""
+    import numpy as np
+    import synth
+    c = CYCLE
+    res = {}
+    for n, N in CYCLE_SHAPES:
+        XB0, obs, r, truths, ys, Es = synth.l96_cycle_inputs(n, N, CYCLE_SHAPE_CYCLES, c["nsteps"], c["seed"] + n + N)
+        dev = lambda a: pk.to_colmajor(a) if a.ndim == 2 else torch.as_tensor(a).cuda()
+        obs_d, r_d = dev(obs), dev(r)
+        ys_d, Es_d = [dev(y) for y in ys], [dev(E) for E in Es]
+        row = {}
+        for algo in ("plain", "blocked"):
+            XB = dev(XB0)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(CYCLE_SHAPE_CYCLES + 1)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            rf, ra = [], []
+            for k, (fmean, amean) in enumerate(pk.cycle_l96(XB, obs_d, ys_d, Es_d, r_d, c["nsteps"], algo=algo)):
+                ev[k + 1].record()
+                rf.append(fmean)
+                ra.append(amean)
+            torch.cuda.synchronize()
+            ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(1, CYCLE_SHAPE_CYCLES)]
+            rmse = lambda x, t: float(np.sqrt(np.mean((x.cpu().numpy() - t) ** 2)))
+            row[algo] = {"ms_per_cycle": round(float(np.mean(ms)), 4),
+                         "rmse_forecast": rmse(rf[-1], truths[-1]), "rmse_analysis": rmse(ra[-1], truths[-1])}
+            print(f"[bench] cycle n={n} N={N} {algo}: {row[algo]['ms_per_cycle']:.3f} ms/cycle, RMSE f "
+                  f"{row[algo]['rmse_forecast']:.5f} a {row[algo]['rmse_analysis']:.5f}", file=sys.stderr, flush=True)
+            del XB
+        res[f"n{n}_N{N}"] = row
+    return res
 
 
 def run_c5(w, args, pk, torch):
