@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void split_b_kernel(int K, int m, const double
 // 4 rows x 4 k (four 16-byte column loads, four 8-byte LDS writes per part);
 // B items: 8 k of one column (one 16-byte load and write per part).
 // 4 waves, 2 x 2: wave (w/2, w%2) owns TC/2 columns x TR/2 rows.
-template <int MATH, int MODE, int TR, int TC, bool VEC>
+template <int MATH, int MODE, int TR, int TC, bool VEC, bool LOOP>
 __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename Lp<MATH>::e_t* __restrict__ Bp,
                                                         int ldk, int64_t bp_stride) {
   typedef Lp<MATH> P;
@@ -284,9 +284,11 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
   __shared__ double mean[TR];
   int64_t rt;
   int ct;
-  // with col_loop one block takes every column tile of its row tile (the row
-  // means of ANALYSIS are then formed once per row tile)
-  xcd_tile_map(blockIdx.x, p.n_row_tiles, p.col_loop ? 1 : p.n_col_tiles, &rt, &ct);
+  // LOOP: one block takes every column tile of its row tile (the row means of
+  // ANALYSIS are then formed once per row tile). It is a separate instance so
+  // that one-tile launches keep their register budget (occupancy).
+  static_assert(!LOOP || MODE == NN_ANALYSIS, "only ANALYSIS walks the column tiles");
+  xcd_tile_map(blockIdx.x, p.n_row_tiles, LOOP ? 1 : p.n_col_tiles, &rt, &ct);
   if (rt >= p.n_row_tiles) return;
   const int64_t row0 = rt * TR;
   const float* __restrict__ A = static_cast<const float*>(p.A);
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
     }
     __syncthreads();
   }
-  const int ct_end = p.col_loop ? p.n_col_tiles : ct + 1;
+  const int ct_end = LOOP ? p.n_col_tiles : ct + 1;
   for (; ct < ct_end; ++ct) {
   const int col0 = ct * TC;
   mf_f4 acc[CI][RJ], acc2[P::has_scaled ? CI : 1][P::has_scaled ? RJ : 1];
@@ -459,11 +461,20 @@ void nn_go(NnArgs p, const typename Lp<MATH>::e_t* Bp, int ldk, int64_t stride, 
   p.n_col_tiles = (p.m + TC - 1) / TC;
   // ANALYSIS with several column tiles and rows enough to fill the part: one
   // block per row tile walks its column tiles (row means formed once)
-  p.col_loop = (MODE == NN_ANALYSIS && p.n_col_tiles > 1 && p.n_row_tiles >= 2048) ? 1 : 0;
+  // the walk over column tiles only where its instance keeps every register
+  // (vector loads; the two-part FP16 split would spill)
+  constexpr bool kLoopable = MODE == NN_ANALYSIS && TR == 128 && MATH != ENKF_MATH_F16X2;
+  const bool loop = kLoopable && vec && p.n_col_tiles > 1 && p.n_row_tiles >= 2048;
   const int64_t groups = (p.n_row_tiles + 7) / 8;
-  const unsigned g = (unsigned)(groups * 8 * (p.col_loop ? 1 : p.n_col_tiles));
-  if (vec) nn_lowp_kernel<MATH, MODE, TR, TC, true><<<g, NT, 0, s>>>(p, Bp, ldk, stride);
-  else nn_lowp_kernel<MATH, MODE, TR, TC, false><<<g, NT, 0, s>>>(p, Bp, ldk, stride);
+  const unsigned g = (unsigned)(groups * 8 * (loop ? 1 : p.n_col_tiles));
+  if constexpr (kLoopable) {
+    if (loop) {
+      nn_lowp_kernel<MATH, MODE, TR, TC, true, true><<<g, NT, 0, s>>>(p, Bp, ldk, stride);
+      return;
+    }
+  }
+  if (vec) nn_lowp_kernel<MATH, MODE, TR, TC, true, false><<<g, NT, 0, s>>>(p, Bp, ldk, stride);
+  else nn_lowp_kernel<MATH, MODE, TR, TC, false, false><<<g, NT, 0, s>>>(p, Bp, ldk, stride);
 }
 
 template <int MATH>

@@ -21,7 +21,6 @@ struct NnArgs {
   void* bws;                         // workspace: Bm converted (nn_bt_bytes(K, m) bytes)
   int64_t n_row_tiles;               // set by the launcher
   int n_col_tiles;                   // set by the launcher
-  int col_loop;                      // set by the launcher: a block takes all column tiles of its row tile
 };
 
 // G (a x m, FP64, ldg) = A^T B with split-K partials (partial must hold

@@ -289,8 +289,9 @@ __global__ __launch_bounds__(256) void convert_b_kernel(int K, int m, const doub
 // 16-byte LDS writes along rows/columns, conflict-free MFMA operand reads.
 // Waves 2 x 2: wave (w/2, w%2) owns TC/2 columns x TR/2 rows. One LDS
 // buffer; the next stage is prefetched into registers.
-template <typename T, int MODE, int TR, int TC, bool VEC>
+template <typename T, int MODE, int TR, int TC, bool VEC, bool LOOP>
 __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ Bt, int ldbc) {
+  static_assert(!LOOP || MODE == NN_ANALYSIS, "only ANALYSIS walks the column tiles");
   typedef typename MfOf<T>::type MF;
   typedef typename V16<T>::type vt;
   constexpr int W = V16<T>::W;
@@ -309,9 +310,10 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
   __shared__ double mean[TR];
   int64_t rt;
   int ct;
-  // with col_loop one block takes every column tile of its row tile (the row
-  // means of ANALYSIS are then formed once per row tile)
-  xcd_tile_map(blockIdx.x, p.n_row_tiles, p.col_loop ? 1 : p.n_col_tiles, &rt, &ct);
+  // LOOP: one block takes every column tile of its row tile (the row means of
+  // ANALYSIS are then formed once per row tile). It is a separate instance so
+  // that one-tile launches keep their register budget (occupancy).
+  xcd_tile_map(blockIdx.x, p.n_row_tiles, LOOP ? 1 : p.n_col_tiles, &rt, &ct);
   if (rt >= p.n_row_tiles) return;
   const int64_t row0 = rt * TR;
   const T* __restrict__ A = static_cast<const T*>(p.A);
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
     __syncthreads();
   }
 
-  const int ct_end = p.col_loop ? p.n_col_tiles : ct + 1;
+  const int ct_end = LOOP ? p.n_col_tiles : ct + 1;
   for (; ct < ct_end; ++ct) {
   const int col0 = ct * TC;
   typename MF::acc_t acc[CI][RJ];
@@ -687,12 +689,20 @@ enkf_status nn_go(NnArgs p, const T* Bt, int ldbc, bool vec, hipStream_t s) {
   p.n_col_tiles = (p.m + TC - 1) / TC;
   // ANALYSIS with several column tiles and rows enough to fill the part: one
   // block per row tile walks its column tiles (row means formed once)
-  p.col_loop = (MODE == NN_ANALYSIS && p.n_col_tiles > 1 && p.n_row_tiles >= kNnLoopRowTiles) ? 1 : 0;
+  const bool loop = MODE == NN_ANALYSIS && p.n_col_tiles > 1 && p.n_row_tiles >= kNnLoopRowTiles;
   const int64_t groups = (p.n_row_tiles + 7) / 8;
-  const int64_t blocks = groups * 8 * (p.col_loop ? 1 : p.n_col_tiles);
+  const int64_t blocks = groups * 8 * (loop ? 1 : p.n_col_tiles);
   if (blocks > 0x7fffffff) return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
-  if (vec) nn_kernel<T, MODE, TR, TC, true><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
-  else nn_kernel<T, MODE, TR, TC, false><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
+  if constexpr (MODE == NN_ANALYSIS && TR == 128) {   // the tiles taken when m > 128
+    if (loop) {
+      if (vec) nn_kernel<T, MODE, TR, TC, true, true><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
+      else nn_kernel<T, MODE, TR, TC, false, true><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
+      ENKF_HIP_CHECK(hipGetLastError());
+      return ENKF_SUCCESS;
+    }
+  }
+  if (vec) nn_kernel<T, MODE, TR, TC, true, false><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
+  else nn_kernel<T, MODE, TR, TC, false, false><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
