@@ -89,6 +89,34 @@ def gpu_inputs(w, dtype, pk, torch):
     return d
 
 
+def cpu_model() -> str:
+    """The host processor's model name (the cores the oracle ran on)."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def timed_steps(torch, step, steps):
+    """Time `steps` calls of step() with HIP events on the current stream (the
+    one the library launches on): one event before the first step and one
+    after each. Returns (mean, median, min) milliseconds per step; the mean is
+    over the whole bracket."""
+    import numpy as np
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i in range(steps):
+        step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return ev[0].elapsed_time(ev[-1]) / steps, float(np.median(per)), float(min(per))
+
+
 def run_form(name, w, args, pk, torch, cache):
     import numpy as np
     algo, storage, math, refine = FORMS[name]
@@ -141,14 +169,7 @@ def run_form(name, w, args, pk, torch, cache):
         step()
     torch.cuda.synchronize()
     info = plan.info()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / steps
+    ms, ms_med, ms_min = timed_steps(torch, step, steps)
     print(f"[bench] {name}: {ms:.3f} ms/step over {steps} steps", file=sys.stderr, flush=True)
     # per-kernel durations, HIP events on the plan's stream, same workload
     plan.set_timing(True)
@@ -179,7 +200,8 @@ def run_form(name, w, args, pk, torch, cache):
         rho = Dh - w.r[:, None] * Zh - Vh @ (Vh.T @ Zh)
     relres = float(np.linalg.norm(rho) / np.linalg.norm(Dh))
     del Vh, Dh, Zh, rho
-    out = {"ms_per_step": round(ms, 4), "solves_per_s": round(1000.0 / ms, 3), "algo": algo, "storage": storage,
+    out = {"ms_per_step": round(ms, 4), "ms_median": round(ms_med, 4), "ms_min": round(ms_min, 4),
+           "solves_per_s": round(1000.0 / ms, 3), "algo": algo, "storage": storage,
            "math": math, "refine_iters": last["info"]["refine_iters"] if refine else 0,
            "device_rel_residual": last["info"]["rel_residual"] if refine else None, "block": (args.block or min(w.n_ens, 128)) if algo == "blocked" else 1,
            "rel_residual": relres, "gamma_range": [info["gamma_min"], info["gamma_max"]], "kernels": kern}
@@ -260,7 +282,7 @@ def cpu_baseline(w, args):
     else:
         what = (f"{reps} solve(s) on the first {w.n_obs // 32} of {w.n_obs} observations, FP64, {el:.1f} s, "
                 f"time scaled by {scale:.0f} (cost linear in n)")
-    return {"value": round(reps / (el * scale), 5), "unit": "solves/s", "cores": threads, "kind": "oracle",
+    return {"value": round(reps / (el * scale), 5), "unit": "solves/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
             "sample": what}
 
 
@@ -280,15 +302,8 @@ def run_local(w, args, pk, torch):
     cfg = plan.sync()
     for _ in range(args.warmup):
         plan.analysis(r, Vd, Dd, XBd, XA)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        plan.analysis(r, Vd, Dd, XBd, XA)
-    ev1.record()
-    torch.cuda.synchronize()
+    ms, ms_med, ms_min = timed_steps(torch, lambda: plan.analysis(r, Vd, Dd, XBd, XA), args.steps)
     plan.sync()
-    ms = ev0.elapsed_time(ev1) / args.steps
     N = w.n_ens
     # algorithmic work: the level iteration of every local solve (6 N^2 n_p)
     # plus its local analysis (2 N^2 n_p + N^2); the kernel itself runs the
@@ -307,7 +322,8 @@ def run_local(w, args, pk, torch):
                 "kernel": "local_kernel (all local analyses, one graph-replayed launch)",
                 "avg_launch_us": round(ms * 1e3, 2), "alg_flops_per_launch": flops,
                 "mfma_flops_per_launch": mfma_flops,
-                "mfma_TFLOP/s": round(mfma_flops / (ms * 1e-3) / 1e12, 3)}, cfg, err
+                "mfma_TFLOP/s": round(mfma_flops / (ms * 1e-3) / 1e12, 3),
+                "step_ms_median": round(ms_med, 4), "step_ms_min": round(ms_min, 4)}, cfg, err
 
 
 def run_loc(w, args, pk, torch):
@@ -331,14 +347,8 @@ def run_loc(w, args, pk, torch):
         for _ in range(args.warmup):
             plan.localized_analysis(XB, Z, loc, length, -1, ring, XA)
         plan.set_timing(True)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        ev0.record()
-        for _ in range(args.steps):
-            plan.localized_analysis(XB, Z, loc, length, -1, ring, XA)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.steps
+        ms, ms_med, ms_min = timed_steps(torch, lambda: plan.localized_analysis(XB, Z, loc, length, -1, ring, XA),
+                                         args.steps)
         t = plan.timing("localize")
         avg_us = t["ms"] * 1e3 / max(t["launches"], 1)
         flops = 4.0 * w.n_state * w.n_obs * w.n_ens
@@ -351,7 +361,8 @@ def run_loc(w, args, pk, torch):
         got = XA[rows[0]:rows[1]].cpu().numpy().astype(np.float64)
         corr = np.abs(ref - XBh[rows[0]:rows[1]]).max()
         err = float(np.abs(got - ref).max() / corr)
-        out["localized_" + storage] = {"ms_per_step": round(ms, 4), "analyses_per_s": round(1e3 / ms, 3),
+        out["localized_" + storage] = {"ms_per_step": round(ms, 4), "ms_median": round(ms_med, 4),
+                                       "ms_min": round(ms_min, 4), "analyses_per_s": round(1e3 / ms, 3),
                                        "avg_launch_us": round(avg_us, 2), "alg_flops_per_launch": flops,
                                        "TFLOP/s": round(ach, 2), "sampled_rel_err_vs_oracle": err}
         plan.close()
@@ -470,14 +481,7 @@ def run_c5(w, args, pk, torch):
     def timed(fn, steps):
         for _ in range(args.warmup):
             fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
+        return timed_steps(torch, fn, steps)
 
     # (a) FP32 blocked, build + factor + solve + analysis (FP32)
     pa = pk.Plan(r, V32, algo="blocked", block=args.block)
@@ -487,13 +491,14 @@ def run_c5(w, args, pk, torch):
         pa.refactor(r, V32)
         pa.solve(D32, Z32)
         pa.analysis(XB, Z32, XA)
-    ms_a = timed(step_a, args.steps)
+    ms_a, med_a, min_a = timed(step_a, args.steps)
     pa.set_timing(True)
     step_a()
     torch.cuda.synchronize()
     ka = {c: pa.timing(c) for c in CLASSES}
     pa.set_timing(False)
-    res["blocked_f32"] = {"ms_per_step": round(ms_a, 3), "solves_per_s": round(1000 / ms_a, 4),
+    res["blocked_f32"] = {"ms_per_step": round(ms_a, 3), "ms_median": round(med_a, 3), "ms_min": round(min_a, 3),
+                          "solves_per_s": round(1000 / ms_a, 4),
                           "kernels": {c: {"ms": round(v["ms"], 3), "launches": v["launches"],
                                           "TFLOP/s": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] else None}
                                       for c, v in ka.items() if v["launches"]}}
@@ -509,13 +514,14 @@ def run_c5(w, args, pk, torch):
         pb.refactor(r, V64)
         _, last["info"] = pb.solve(D64, Z64, info=True)
         pb.analysis_ex(XB, Z64, XA, math="f32")
-    ms_b = timed(step_b, max(1, args.steps))
+    ms_b, med_b, min_b = timed(step_b, max(1, args.steps))
     pb.set_timing(True)
     step_b()
     torch.cuda.synchronize()
     kb = {c: pb.timing(c) for c in CLASSES}
     pb.set_timing(False)
-    res["mixed_f32"] = {"ms_per_step": round(ms_b, 3), "solves_per_s": round(1000 / ms_b, 4),
+    res["mixed_f32"] = {"ms_per_step": round(ms_b, 3), "ms_median": round(med_b, 3), "ms_min": round(min_b, 3),
+                        "solves_per_s": round(1000 / ms_b, 4),
                         "refine_iters": last["info"]["refine_iters"], "rel_residual": last["info"]["rel_residual"],
                         "kernels": {c: {"ms": round(v["ms"], 3), "launches": v["launches"],
                                         "TFLOP/s": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] else None}
@@ -523,7 +529,7 @@ def run_c5(w, args, pk, torch):
     # the analysis product alone, FP32 and BF16 inputs
     an = {}
     for math in ("f32", "bf16"):
-        ms = timed(lambda: pb.analysis_ex(XB, Z64, XA, math=math), max(2, args.steps))
+        ms = timed(lambda: pb.analysis_ex(XB, Z64, XA, math=math), max(2, args.steps))[0]
         flops = 2.0 * w.n_state * N * N
         an[math] = {"ms": round(ms, 3), "TFLOP/s_incl_VtZ": round(flops / (ms * 1e-3) / 1e12, 2)}
     res["analysis_product"] = an
@@ -605,7 +611,7 @@ def main():
             oracle.local_analysis(w.r, V, D, w.XB, w.extra["win_start"], w.extra["win_len"], w.extra["state_idx"])
             el = time.perf_counter() - c0
             threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-            base = {"value": round(P / el, 2), "unit": "local analyses/s", "cores": threads, "kind": "oracle",
+            base = {"value": round(P / el, 2), "unit": "local analyses/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
                     "sample": f"all {P} local analyses of the same workload in FP64 (plain level iteration), {el:.2f} s"}
         out = {"metric": METRIC, "value": round(P / (ms * 1e-3), 1), "unit": "local analyses/s", "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
@@ -635,7 +641,7 @@ def main():
             el = time.perf_counter() - c0
             threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
             base = {"value": round(k / el / w.n_state, 6), "unit": "localized analyses/s", "cores": threads,
-                    "kind": "oracle", "sample": f"{k} of {w.n_state} state rows of the same update in FP64 "
+                    "kind": "oracle", "cpu": cpu_model(), "sample": f"{k} of {w.n_state} state rows of the same update in FP64 "
                                                 f"({el:.2f} s), scaled to whole analyses"}
         ach = head["TFLOP/s"]
         out = {"metric": METRIC, "value": head["analyses_per_s"], "unit": "localized analyses/s", "n_gpus": 1,
@@ -665,7 +671,7 @@ def main():
             oracle.cycle_l96(XB0, obs, ys[:k], Es[:k], r, CYCLE["nsteps"])
             el = time.perf_counter() - c0
             threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-            base = {"value": round(k / el, 4), "unit": "cycles/s", "cores": threads, "kind": "oracle",
+            base = {"value": round(k / el, 4), "unit": "cycles/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
                     "sample": f"the first {k} cycles of the same run in FP64 ({el:.2f} s)"}
         out = {"metric": METRIC, "value": head["cycles_per_s"], "unit": "cycles/s", "n_gpus": 1,
                "steps": CYCLE["cycles"], "warmup": args.warmup, "ms_per_step": head["ms_per_cycle"],

@@ -18,14 +18,16 @@ enkf_status launch_small_gemm(int b, int m, const double* Minv, const double* Pr
                               hipStream_t s);
 
 // FP64 -> FP32 copy divided by the rms of X (sumsq: device ||X||_F^2, or
-// NULL for no scaling); FP32 -> FP64 copy or accumulation multiplied back.
+// NULL for no scaling) and, with r, by r_i row by row (Step 1 fused; bad r_i
+// latch NOT_SPD in status); FP32 -> FP64 copy or accumulation multiplied back.
 enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float* Y, int64_t ldy, const double* sumsq,
-                           hipStream_t s);
+                           const double* r, unsigned* status, hipStream_t s);
 // Z += X, FP64.
 enkf_status launch_add(int64_t n, int m, const double* X, int64_t ldx, double* Z, int64_t ldz, hipStream_t s);
 enkf_status launch_widen(int64_t n, int m, const float* W, int64_t ldw, double* Z, int64_t ldz, bool accumulate,
                          const double* sumsq, hipStream_t s);
-// out[0] = ||X||_F^2, out[1] = ||Y||_F^2 (fixed-order two-stage sums).
+// out[0] = ||X||_F^2 and, when Y is given, out[1] = ||Y||_F^2 (out[1] is
+// left alone otherwise); fixed-order two-stage sums.
 int norm_partial_elems();
 enkf_status launch_sumsq2(int64_t n, int m, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* part,
                           double* out, hipStream_t s);

@@ -255,13 +255,21 @@ __device__ __forceinline__ double rms_scale(const double* sumsq, double count) {
 }
 
 // Y = X / scale in FP32 (scale = rms of X when sumsq is given), so a
-// shrinking residual stays inside the range of the narrow input types.
+// shrinking residual stays inside the range of the narrow input types. With
+// r, also Step 1 of the solve in the same pass: Y = R^{-1} X / scale, one
+// rounding to FP32; latches NOT_SPD for r_i <= 0 or non-finite.
 __global__ __launch_bounds__(256) void convert_kernel(int64_t n, int m, const double* __restrict__ X, int64_t ldx,
-                                                      float* __restrict__ Y, int64_t ldy, const double* sumsq) {
+                                                      float* __restrict__ Y, int64_t ldy, const double* sumsq,
+                                                      const double* __restrict__ r, unsigned* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double inv = 1.0 / rms_scale(sumsq, (double)n * m);
-  for (int j = blockIdx.y; j < m; j += gridDim.y) Y[i + (int64_t)j * ldy] = (float)(X[i + (int64_t)j * ldx] * inv);
+  double div = rms_scale(sumsq, (double)n * m);
+  if (r) {
+    const double rv = r[i];
+    if (blockIdx.y == 0 && (!(rv > 0.0) || !__builtin_isfinite(rv))) atomicOr(status, kStatusNotSpd);
+    div *= rv;
+  }
+  for (int j = blockIdx.y; j < m; j += gridDim.y) Y[i + (int64_t)j * ldy] = (float)(X[i + (int64_t)j * ldx] / div);
 }
 
 // Z = scale W (accumulate == 0) or Z += scale W (accumulate == 1), W in FP32.
@@ -288,8 +296,8 @@ __global__ __launch_bounds__(256) void add_kernel(int64_t n, int m, const double
 
 constexpr int NORM_BLOCKS = 1024;
 
-// Per-block partial sums of squares of two n x m FP64 matrices, in a fixed
-// order; then one block sums the partials.
+// Per-block partial sums of squares of one or two (Y != NULL) n x m FP64
+// matrices, in a fixed order; then one block sums the partials.
 __global__ __launch_bounds__(256) void sumsq_partial_kernel(int64_t n, int m, const double* __restrict__ X, int64_t ldx,
                                                             const double* __restrict__ Y, int64_t ldy,
                                                             double* __restrict__ part) {
@@ -298,9 +306,12 @@ __global__ __launch_bounds__(256) void sumsq_partial_kernel(int64_t n, int m, co
   double sx = 0.0, sy = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     const int64_t i = e % n, j = e / n;
-    const double x = X[i + j * ldx], y = Y[i + j * ldy];
+    const double x = X[i + j * ldx];
     sx += x * x;
-    sy += y * y;
+    if (Y) {
+      const double y = Y[i + j * ldy];
+      sy += y * y;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     sx += __shfl_xor(sx, off, 64);
@@ -315,14 +326,18 @@ __global__ __launch_bounds__(256) void sumsq_partial_kernel(int64_t n, int m, co
   }
 }
 
-__global__ __launch_bounds__(64) void sumsq_final_kernel(int nblk, const double* __restrict__ part, double* __restrict__ out) {
+__global__ __launch_bounds__(64) void sumsq_final_kernel(int nblk, int two, const double* __restrict__ part,
+                                                         double* __restrict__ out) {
   double sx = 0.0, sy = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) { sx += part[2 * b]; sy += part[2 * b + 1]; }
   for (int off = 32; off > 0; off >>= 1) {
     sx += __shfl_xor(sx, off, 64);
     sy += __shfl_xor(sy, off, 64);
   }
-  if (threadIdx.x == 0) { out[0] = sx; out[1] = sy; }
+  if (threadIdx.x == 0) {
+    out[0] = sx;
+    if (two) out[1] = sy;
+  }
 }
 
 }  // namespace
@@ -330,10 +345,11 @@ __global__ __launch_bounds__(64) void sumsq_final_kernel(int nblk, const double*
 int norm_partial_elems() { return 2 * NORM_BLOCKS; }
 
 enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float* Y, int64_t ldy, const double* sumsq,
-                           hipStream_t s) {
+                           const double* r, unsigned* status, hipStream_t s) {
   if (m <= 0) return ENKF_SUCCESS;
+  if (r && !status) return fail(ENKF_ERR_INVALID_ARG, "convert: row scaling needs the status word");
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)(m < 16 ? m : 16));
-  convert_kernel<<<grid, 256, 0, s>>>(n, m, X, ldx, Y, ldy, sumsq);
+  convert_kernel<<<grid, 256, 0, s>>>(n, m, X, ldx, Y, ldy, sumsq, r, status);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
@@ -355,7 +371,7 @@ enkf_status launch_sumsq2(int64_t n, int m, const double* X, int64_t ldx, const 
   if (nblk < 1) nblk = 1;
   sumsq_partial_kernel<<<nblk, 256, 0, s>>>(n, m, X, ldx, Y, ldy, part);
   ENKF_HIP_CHECK(hipGetLastError());
-  sumsq_final_kernel<<<1, 64, 0, s>>>(nblk, part, out);
+  sumsq_final_kernel<<<1, 64, 0, s>>>(nblk, Y ? 1 : 0, part, out);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }

@@ -88,10 +88,13 @@ struct Plan {
   enkf_status block_step1(enkf_dtype dt, int m, const void* X, int64_t ldx, void* Y, int64_t ldy);
   enkf_status factor_blocked();
   // Z = (R + V V^T)^{-1} D with the blocked factor, all in the working type.
-  enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz);
+  // step1_done: Z already holds R^{-1} D (D is not read).
+  enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool step1_done = false);
   enkf_status solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
   enkf_status solve_refined64(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
-  enkf_status residual64(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz);
+  // rho = D - W Z in FP64, ||rho||^2 into norms[0] and, with d_norm,
+  // ||D||^2 into norms[1] (constant over one solve, so formed once).
+  enkf_status residual64(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz, bool d_norm);
   const void* vwork() const { return mixed ? Vw : V; }
   int64_t ldvw() const { return mixed ? ldu : ldv; }
   const void* vcol(int k) const;  // V column used at level k

@@ -554,7 +554,8 @@ enkf_status Plan::factor_blocked() {
   const size_t wes = dtype_size(wdt);
   enkf_status st;
   if (mixed) {
-    st = launch_convert(n, N, static_cast<const double*>(V), ldv, static_cast<float*>(Vw), ldu, nullptr, stream);
+    st = launch_convert(n, N, static_cast<const double*>(V), ldv, static_cast<float*>(Vw), ldu, nullptr, nullptr,
+                        nullptr, stream);
     if (st != ENKF_SUCCESS) return st;
   }
   const void* Vk = vwork();
@@ -611,12 +612,12 @@ enkf_status Plan::factor_blocked() {
 }
 
 // Z = W^{-1} D in the working type (D may be Z itself).
-enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz) {
+enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool step1_done) {
   const int64_t n = desc.n_obs;
   const size_t wes = dtype_size(wdt);
   enkf_status st;
   if (nrhs == 0) return ENKF_SUCCESS;
-  {
+  if (!step1_done) {
     TimedLaunch tl(&timing, stream, KC_STEP1, 2.0 * n * nrhs * wes + 8.0 * n, (double)n * nrhs);
     st = block_r ? launch_block_solve(wdt, max_bs, nblk, nrhs, boff, bpoff, Lf, D, ldd, Z, ldz, stream)
                  : launch_scale_rows(wdt, n, nrhs, D, ldd, r, Z, ldz, status, stream);
@@ -661,23 +662,24 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
 }
 
 // Mixed precision: Z0 = W~^{-1} D with FP32 panels, then Z += W~^{-1} rho
-// with rho = D - (R Z + V (V^T Z)) formed in FP64.
+// with rho = D - (R Z + V (V^T Z)) formed in FP64. The narrowing copy of D
+// or rho also applies R^{-1} (Step 1), so the panels start from it.
 enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync) {
   const int64_t n = desc.n_obs;
   last.refine_iters = 0;
   last.rel_residual = -1.0;
   if (nrhs == 0) return ENKF_SUCCESS;
   float* W = static_cast<float*>(Zw);
-  enkf_status st = launch_convert(n, nrhs, static_cast<const double*>(D), ldd, W, ldu, nullptr, stream);
+  enkf_status st = launch_convert(n, nrhs, static_cast<const double*>(D), ldd, W, ldu, nullptr, r, status, stream);
   if (st != ENKF_SUCCESS) return st;
-  st = solve_blocked(nrhs, W, ldu, W, ldu);
+  st = solve_blocked(nrhs, W, ldu, W, ldu, true);
   if (st != ENKF_SUCCESS) return st;
   st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, false, nullptr, stream);
   if (st != ENKF_SUCCESS) return st;
   const int maxit = desc.refine_max_iter;
   for (int it = 0; it <= maxit; ++it) {
     if (!sync && it == maxit) break;
-    st = residual64(nrhs, D, ldd, Z, ldz);
+    st = residual64(nrhs, D, ldd, Z, ldz, it == 0);
     if (st != ENKF_SUCCESS) return st;
     if (sync) {
       double h[2];
@@ -686,9 +688,9 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
       last.rel_residual = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
       if (last.rel_residual <= desc.refine_tol || it == maxit) break;
     }
-    st = launch_convert(n, nrhs, rho, ldu, W, ldu, norms, stream);
+    st = launch_convert(n, nrhs, rho, ldu, W, ldu, norms, r, status, stream);
     if (st != ENKF_SUCCESS) return st;
-    st = solve_blocked(nrhs, W, ldu, W, ldu);
+    st = solve_blocked(nrhs, W, ldu, W, ldu, true);
     if (st != ENKF_SUCCESS) return st;
     st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, true, norms, stream);
     if (st != ENKF_SUCCESS) return st;
@@ -709,7 +711,7 @@ enkf_status Plan::solve_refined64(int nrhs, const void* D, int64_t ldd, void* Z,
   const int maxit = desc.refine_max_iter;
   for (int it = 0; it <= maxit; ++it) {
     if (!sync && it == maxit) break;
-    st = residual64(nrhs, D, ldd, Z, ldz);
+    st = residual64(nrhs, D, ldd, Z, ldz, it == 0);
     if (st != ENKF_SUCCESS) return st;
     if (sync) {
       double h[2];
@@ -727,8 +729,9 @@ enkf_status Plan::solve_refined64(int nrhs, const void* D, int64_t ldd, void* Z,
   return ENKF_SUCCESS;
 }
 
-// rho = D - (r o Z + V (V^T Z)) in FP64 and the squared norms of rho and D.
-enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz) {
+// rho = D - (r o Z + V (V^T Z)) in FP64 and the squared norms of rho and
+// (d_norm) D.
+enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz, bool d_norm) {
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
   enkf_status st;
@@ -760,7 +763,8 @@ enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z
     if (st != ENKF_SUCCESS) return st;
   }
   // ||rho||^2 and ||D||^2: the convergence test and the scale of rho
-  return launch_sumsq2(n, nrhs, rho, ldu, static_cast<const double*>(D), ldd, norms + 2, norms, stream);
+  return launch_sumsq2(n, nrhs, rho, ldu, d_norm ? static_cast<const double*>(D) : nullptr, ldd, norms + 2, norms,
+                       stream);
 }
 
 // ------------------------------------------------------------------ common

@@ -166,3 +166,22 @@ def test_blocked_fp64_refinement_restores_accuracy():
     assert info["refine_iters"] == 2
     assert rr <= max(1e-12, 2.0 * rr_or), (rr, rr_or, rr0)
     assert rr < rr0
+
+
+def test_mixed_solve_latches_bad_r():
+    """The mixed form applies R^{-1} while narrowing D and each residual
+    (Step 1 fused into that copy); a non-positive r_i seen there latches
+    NOT_SPD like the separate Step 1 does. The plan borrows r, so r is spoiled
+    on the device after the (valid) factorization."""
+    import torch
+    pk = _pk()
+    n, N = 1000, 16
+    r, V, D = synth.small_vd(n, N, seed=78)
+    rd = dev(r)
+    plan = pk.Plan(rd, dev(V), algo="blocked", math="f32", block=16, refine_max_iter=2, refine_tol=1e-12)
+    torch.cuda.synchronize()
+    rd[5] = -1.0
+    with pytest.raises(pk.EnkfError) as e:
+        plan.solve(dev(D), info=True)
+    assert e.value.code == 2
+    plan.close()
