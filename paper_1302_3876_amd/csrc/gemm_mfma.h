@@ -19,6 +19,8 @@ struct NnArgs {
   const void* Din; int64_t ldd;      // RESIDUAL: D
   const double* r;                   // RESIDUAL: diag(R)
   void* bws;                         // workspace: Bm converted (nn_bt_bytes(K, m) bytes)
+  double* part; int64_t part_cap;    // RESIDUAL, optional: per-block sums of rho^2 (capacity in doubles)
+  double* sumsq;                     // RESIDUAL with part: ||rho||_F^2, the partials summed in a fixed order
   int64_t n_row_tiles;               // set by the launcher
   int n_col_tiles;                   // set by the launcher
 };
@@ -30,6 +32,9 @@ enkf_status launch_tn(enkf_dtype dt, int64_t n, int a, int m, const void* A, int
                       double* G, int64_t ldg, double* partial, hipStream_t s);
 
 enkf_status launch_nn(enkf_dtype dt, int mode, NnArgs p, hipStream_t s);
+// Capacity (doubles) of NnArgs::part that any RESIDUAL product with n rows
+// and at most m columns needs.
+int64_t nn_residual_part_elems(int64_t n, int m);
 // Converted right factor of an nn product: padded rows (multiple of 32),
 // padded columns (multiple of 128), workspace bytes.
 int nn_bt_rows(int K);

@@ -314,7 +314,11 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
   // ANALYSIS are then formed once per row tile). It is a separate instance so
   // that one-tile launches keep their register budget (occupancy).
   xcd_tile_map(blockIdx.x, p.n_row_tiles, LOOP ? 1 : p.n_col_tiles, &rt, &ct);
-  if (rt >= p.n_row_tiles) return;
+  if (rt >= p.n_row_tiles) {
+    // a padding block of the grid: its share of ||rho||^2 is zero
+    if (MODE == NN_RESIDUAL && p.part && threadIdx.x == 0) p.part[blockIdx.x] = 0.0;
+    return;
+  }
   const int64_t row0 = rt * TR;
   const T* __restrict__ A = static_cast<const T*>(p.A);
   const int t = threadIdx.x, l = t % kWave, w = t / kWave;
@@ -433,6 +437,7 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
   const T* __restrict__ Cin = static_cast<const T*>(p.Cin);
   const T* __restrict__ Din = static_cast<const T*>(p.Din);
   T* __restrict__ Cout = static_cast<T*>(p.Cout);
+  double ss = 0.0;   // RESIDUAL: this thread's sum of the stored rho^2
 #pragma unroll
   for (int i = 0; i < CI; ++i) {
     T cin[RJ][4], din[RJ][4];
@@ -460,10 +465,35 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
         if constexpr (MODE == NN_UPDATE) out = c - prod;
         else if constexpr (MODE == NN_ANALYSIS) out = c + prod;
         else out = (double)din[j][r] - (rr[j] * c + prod);
-        if (col < p.m && row < p.n) Cout[row + (int64_t)col * p.ldo] = (T)out;
+        const bool in = col < p.m && row < p.n;
+        if (in) Cout[row + (int64_t)col * p.ldo] = (T)out;
+        if constexpr (MODE == NN_RESIDUAL) ss += in ? out * out : 0.0;
       }
   }
+  if constexpr (MODE == NN_RESIDUAL) {
+    // the block's share of ||rho||^2: lanes, then the 4 waves, in a fixed order
+    if (p.part) {
+      static_assert(NT == 4 * kWave, "four waves per block");
+      __shared__ double red[4];
+      for (int off = kWave / 2; off > 0; off >>= 1) ss += __shfl_xor(ss, off, kWave);
+      if (l == 0) red[w] = ss;
+      __syncthreads();
+      if (t == 0) p.part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    }
   }
+  }
+}
+
+// out[0] = sum of part[0..count) in a fixed order (one block).
+__global__ __launch_bounds__(256) void part_sum_kernel(int64_t count, const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < count; b += 256) s += part[b];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // ---------------------------------------------------------------- analysis, small N
@@ -679,6 +709,12 @@ constexpr int64_t kNnLoopRowTiles = 2048;   // ~8 row tiles per CU
 int nn_bt_rows(int K) { return (K + 31) / 32 * 32; }
 int nn_bt_cols(int m) { return (m + 127) / 128 * 128; }
 
+// the largest RESIDUAL grid: row tiles of 64 (m <= 128) or 128, padded to a
+// multiple of 8, times column tiles of at least 64
+int64_t nn_residual_part_elems(int64_t n, int m) {
+  return ((n + 63) / 64 + 7) / 8 * 8 * std::max<int64_t>(1, ((int64_t)m + 63) / 64);
+}
+
 size_t nn_bt_bytes(int K, int m) { return sizeof(double) * (size_t)nn_bt_rows(K) * (size_t)nn_bt_cols(m); }
 
 namespace {
@@ -693,6 +729,10 @@ enkf_status nn_go(NnArgs p, const T* Bt, int ldbc, bool vec, hipStream_t s) {
   const int64_t groups = (p.n_row_tiles + 7) / 8;
   const int64_t blocks = groups * 8 * (loop ? 1 : p.n_col_tiles);
   if (blocks > 0x7fffffff) return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
+  if constexpr (MODE == NN_RESIDUAL) {
+    if (p.part && (blocks > p.part_cap || !p.sumsq))
+      return fail(ENKF_ERR_INVALID_ARG, "residual product: norm partials too small or no output");
+  }
   if constexpr (MODE == NN_ANALYSIS && TR == 128) {   // the tiles taken when m > 128
     if (loop) {
       if (vec) nn_kernel<T, MODE, TR, TC, true, true><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
@@ -704,6 +744,12 @@ enkf_status nn_go(NnArgs p, const T* Bt, int ldbc, bool vec, hipStream_t s) {
   if (vec) nn_kernel<T, MODE, TR, TC, true, false><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
   else nn_kernel<T, MODE, TR, TC, false, false><<<(unsigned)blocks, NT, 0, s>>>(p, Bt, ldbc);
   ENKF_HIP_CHECK(hipGetLastError());
+  if constexpr (MODE == NN_RESIDUAL) {
+    if (p.part) {
+      part_sum_kernel<<<1, 256, 0, s>>>(blocks, p.part, p.sumsq);
+      ENKF_HIP_CHECK(hipGetLastError());
+    }
+  }
   return ENKF_SUCCESS;
 }
 

@@ -44,6 +44,8 @@ struct Plan {
   void* Zw = nullptr;           // FP32 correction (mixed), n x max_nrhs
   double* rho = nullptr;        // FP64 residual (mixed), n x max_nrhs
   double* norms = nullptr;      // [0] ||rho||^2, [1] ||D||^2 (mixed)
+  double* res_part = nullptr;   // per-block sums of rho^2 of the residual product
+  int64_t res_part_cap = 0;
   // pivoting (plain)
   bool pivot = false;
   int32_t* perm = nullptr;      // V/U column used at each level (device)

@@ -108,7 +108,7 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   const size_t oTn = take(sizeof(double) * (size_t)tnp);
   // right factor of an nn product, converted: inner dimension <= N, columns <= mcols
   const size_t oBt = take(nn_bt_bytes(N, mcols));
-  size_t oP0 = 0, oP1 = 0, oMinv = 0, oPbuf = 0, oQbuf = 0, oVw = 0, oZw = 0, oRho = 0, oNorm = 0;
+  size_t oP0 = 0, oP1 = 0, oMinv = 0, oPbuf = 0, oQbuf = 0, oVw = 0, oZw = 0, oRho = 0, oNorm = 0, oResPart = 0;
   size_t oGc = 0, oCb = 0, oPerm = 0, oRem = 0, oAct = 0;
   if (!blocked) {
     const size_t part_elems = (size_t)level_row_blocks(d.dtype, 1, n) * (N + max_nrhs);
@@ -133,6 +133,8 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   if (mixed || refine64) {
     oRho = take((size_t)ldu * mcols * sizeof(double));
     oNorm = take(sizeof(double) * (2 + (size_t)norm_partial_elems()));
+    res_part_cap = nn_residual_part_elems(n, mcols);
+    oResPart = take(sizeof(double) * (size_t)res_part_cap);
   }
   ws_bytes = off;
   hipError_t e = hipMalloc(&ws, ws_bytes);
@@ -170,6 +172,7 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   if (mixed || refine64) {
     rho = reinterpret_cast<double*>(ws + oRho);
     norms = reinterpret_cast<double*>(ws + oNorm);
+    res_part = reinterpret_cast<double*>(ws + oResPart);
   }
   ENKF_HIP_CHECK(hipMemsetAsync(ws + oStat, 0, sizeof(unsigned) * 4, stream));
   last.rel_residual = -1.0;
@@ -758,13 +761,16 @@ enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z
     a.Din = D;
     a.ldd = ldd;
     a.r = r;
+    a.part = res_part;            // ||rho||^2 (the convergence test and the scale
+    a.part_cap = res_part_cap;    // of rho) from the kernel's own outputs
+    a.sumsq = norms;
     TimedLaunch tl(&timing, stream, KC_RESIDUAL, (double)(N + 3 * nrhs) * n * 8.0, 2.0 * n * N * nrhs);
     st = launch_nn(ENKF_F64, NN_RESIDUAL, a, stream);
     if (st != ENKF_SUCCESS) return st;
   }
-  // ||rho||^2 and ||D||^2: the convergence test and the scale of rho
-  return launch_sumsq2(n, nrhs, rho, ldu, d_norm ? static_cast<const double*>(D) : nullptr, ldd, norms + 2, norms,
-                       stream);
+  // ||D||^2, constant over the solve
+  if (!d_norm) return ENKF_SUCCESS;
+  return launch_sumsq2(n, nrhs, static_cast<const double*>(D), ldd, nullptr, 0, norms + 2, norms + 1, stream);
 }
 
 // ------------------------------------------------------------------ common

@@ -119,6 +119,29 @@ def test_mixed_split_forms_reach_gate_on_c3_like_data(math, maxit):
     assert info["rel_residual"] <= 1e-10
 
 
+@pytest.mark.parametrize("math", ["f32", "bf16x3"])
+@pytest.mark.parametrize("n,N", [(131149, 64), (40077, 160)])
+def test_mixed_device_residual_norm(math, n, N):
+    """||rho|| / ||D|| as the device forms it (the squares of rho summed in the
+    residual product's epilogue, per block then in a fixed order; ||D||^2 once
+    per solve) against the host's FP64 residual of the returned Z. Taken after
+    the first low-precision solve alone (no refinement step), where rho is
+    far above the rounding of its own evaluation. The row counts leave padding
+    blocks in the grid (their partials must be zero); N = 160 takes the
+    128 x 64 tiles with three column tiles."""
+    import torch
+    w = synth.direct_vd_workload("c3-small", n, N, seed=6001)
+    plan = _pk().Plan(dev(w.r), dev(w.V), algo="blocked", math=math, block=32, refine_max_iter=0, refine_tol=0.0)
+    Z, info = plan.solve(dev(w.D), info=True)
+    torch.cuda.synchronize()
+    Zh = host(Z)
+    rho = w.D - w.r[:, None] * Zh - w.V @ (w.V.T @ Zh)
+    rr = np.linalg.norm(rho) / np.linalg.norm(w.D)
+    print(math, n, N, info, rr, flush=True)
+    assert info["refine_iters"] == 0
+    assert abs(info["rel_residual"] - rr) <= 1e-6 * rr
+
+
 @pytest.mark.parametrize("math,tol", [("f32", 2e-5), ("bf16x3", 2e-5), ("f16x2", 2e-5), ("bf16", 2e-2), ("f16", 5e-3)])
 def test_analysis_ex_fp32_ensemble(math, tol):
     """The analysis update on an FP32 ensemble with FP32/narrow matrix-core
