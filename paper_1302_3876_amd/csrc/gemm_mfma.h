@@ -16,6 +16,7 @@ struct NnArgs {
   double scale;                      // Bm is multiplied by scale (ANALYSIS); 1 otherwise
   const void* Cin; int64_t ldc;      // UPDATE: X; ANALYSIS: XB; RESIDUAL: Z
   void* Cout; int64_t ldo;           // UPDATE: X (same as Cin); ANALYSIS: XA; RESIDUAL: rho
+  float* Cout32; int64_t ldo32;      // RESIDUAL, optional: R^{-1} rho in FP32 here instead of rho in Cout
   const void* Din; int64_t ldd;      // RESIDUAL: D
   const double* r;                   // RESIDUAL: diag(R)
   void* bws;                         // workspace: Bm converted (nn_bt_bytes(K, m) bytes)

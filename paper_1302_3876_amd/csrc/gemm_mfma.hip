@@ -454,7 +454,9 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
       }
     }
 #pragma unroll
-    for (int j = 0; j < RJ; ++j)
+    for (int j = 0; j < RJ; ++j) {
+      double rinv = 1.0;
+      if constexpr (MODE == NN_RESIDUAL) rinv = 1.0 / rr[j];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = col0 + c_off + 16 * i + MF::row(l, r);
@@ -466,9 +468,19 @@ __global__ __launch_bounds__(NT) void nn_kernel(NnArgs p, const T* __restrict__ 
         else if constexpr (MODE == NN_ANALYSIS) out = c + prod;
         else out = (double)din[j][r] - (rr[j] * c + prod);
         const bool in = col < p.m && row < p.n;
-        if (in) Cout[row + (int64_t)col * p.ldo] = (T)out;
-        if constexpr (MODE == NN_RESIDUAL) ss += in ? out * out : 0.0;
+        if constexpr (MODE == NN_RESIDUAL) {
+          // the right-hand side of the next low-precision solve, Step 1
+          // applied, or rho itself
+          if (in) {
+            if (p.Cout32) p.Cout32[row + (int64_t)col * p.ldo32] = (float)(out * rinv);
+            else Cout[row + (int64_t)col * p.ldo] = (T)out;
+          }
+          ss += in ? out * out : 0.0;
+        } else {
+          if (in) Cout[row + (int64_t)col * p.ldo] = (T)out;
+        }
       }
+    }
   }
   if constexpr (MODE == NN_RESIDUAL) {
     // the block's share of ||rho||^2: lanes, then the 4 waves, in a fixed order

@@ -95,8 +95,11 @@ struct Plan {
   enkf_status solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
   enkf_status solve_refined64(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
   // rho = D - W Z in FP64, ||rho||^2 into norms[0] and, with d_norm,
-  // ||D||^2 into norms[1] (constant over one solve, so formed once).
-  enkf_status residual64(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz, bool d_norm);
+  // ||D||^2 into norms[1] (constant over one solve, so formed once). With
+  // w32, R^{-1} rho is written there in FP32 (leading dimension ldu) and rho
+  // itself is not stored.
+  enkf_status residual64(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz, bool d_norm,
+                         float* w32 = nullptr);
   const void* vwork() const { return mixed ? Vw : V; }
   int64_t ldvw() const { return mixed ? ldu : ldv; }
   const void* vcol(int k) const;  // V column used at level k

@@ -666,7 +666,10 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
 
 // Mixed precision: Z0 = W~^{-1} D with FP32 panels, then Z += W~^{-1} rho
 // with rho = D - (R Z + V (V^T Z)) formed in FP64. The narrowing copy of D
-// or rho also applies R^{-1} (Step 1), so the panels start from it.
+// or rho also applies R^{-1} (Step 1), so the panels start from it. Inputs
+// with the FP32 exponent range (FP32, BF16 parts) take R^{-1} rho straight
+// from the residual product; the FP16 forms divide rho by its rms first (a
+// shrinking residual would leave the FP16 range), so they keep the copy.
 enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync) {
   const int64_t n = desc.n_obs;
   last.refine_iters = 0;
@@ -679,10 +682,11 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
   if (st != ENKF_SUCCESS) return st;
   st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, false, nullptr, stream);
   if (st != ENKF_SUCCESS) return st;
+  const bool fp16 = desc.math == ENKF_MATH_F16 || desc.math == ENKF_MATH_F16X2;
   const int maxit = desc.refine_max_iter;
   for (int it = 0; it <= maxit; ++it) {
     if (!sync && it == maxit) break;
-    st = residual64(nrhs, D, ldd, Z, ldz, it == 0);
+    st = residual64(nrhs, D, ldd, Z, ldz, it == 0, fp16 ? nullptr : W);
     if (st != ENKF_SUCCESS) return st;
     if (sync) {
       double h[2];
@@ -691,11 +695,13 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
       last.rel_residual = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
       if (last.rel_residual <= desc.refine_tol || it == maxit) break;
     }
-    st = launch_convert(n, nrhs, rho, ldu, W, ldu, norms, r, status, stream);
-    if (st != ENKF_SUCCESS) return st;
+    if (fp16) {
+      st = launch_convert(n, nrhs, rho, ldu, W, ldu, norms, r, status, stream);
+      if (st != ENKF_SUCCESS) return st;
+    }
     st = solve_blocked(nrhs, W, ldu, W, ldu, true);
     if (st != ENKF_SUCCESS) return st;
-    st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, true, norms, stream);
+    st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, true, fp16 ? norms : nullptr, stream);
     if (st != ENKF_SUCCESS) return st;
     last.refine_iters = it + 1;
   }
@@ -734,7 +740,8 @@ enkf_status Plan::solve_refined64(int nrhs, const void* D, int64_t ldd, void* Z,
 
 // rho = D - (r o Z + V (V^T Z)) in FP64 and the squared norms of rho and
 // (d_norm) D.
-enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz, bool d_norm) {
+enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz, bool d_norm,
+                             float* w32) {
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
   enkf_status st;
@@ -758,6 +765,8 @@ enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z
     a.ldc = ldz;
     a.Cout = rho;
     a.ldo = ldu;
+    a.Cout32 = w32;
+    a.ldo32 = ldu;
     a.Din = D;
     a.ldd = ldd;
     a.r = r;
