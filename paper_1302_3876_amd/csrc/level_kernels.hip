@@ -20,7 +20,9 @@
 // and latches a status error if it is not finite or not > 0 (Section 3.3).
 //
 // Layout: column-major, threads own consecutive row chunks of VW elements
-// (16-byte loads), a block owns LV_THREADS*VW*RPT rows of COLS columns.
+// (16-byte loads), a block owns COLS columns of one tile of LV_THREADS*VW*RPT
+// rows or, past kLvMaxRowBlocks tiles, of several consecutive tiles (the
+// partials it sums and leaves are per block, so their number stays bounded).
 #include "enkf_internal.h"
 
 namespace enkf {
@@ -30,6 +32,7 @@ constexpr int LV_THREADS = 256;
 constexpr int LV_WAVES = LV_THREADS / kWave;
 constexpr int LV_COLS = 8;
 constexpr int LV_RPT = 2;
+constexpr int64_t kLvMaxRowBlocks = 256;
 
 template <typename T, int VW> struct VecT;
 template <> struct VecT<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
@@ -103,15 +106,25 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-template <typename T, int VW, bool STEP1, bool LOOKAHEAD, bool OWN_GAMMA>
+// MULTI: the grid has fewer row blocks than tiles and a block walks its
+// consecutive tiles (a separate instance: one-tile launches keep their
+// register budget).
+template <typename T, int VW, bool STEP1, bool LOOKAHEAD, bool OWN_GAMMA, bool MULTI>
 __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
   constexpr int COLS = LV_COLS, RPT = LV_RPT;
+  constexpr int64_t RPB = (int64_t)LV_THREADS * VW * RPT;   // rows of one tile
   const int64_t n = a.n;
   const int nb = gridDim.x;
+  int64_t tile0 = blockIdx.x, tile1 = tile0 + 1;
+  if constexpr (MULTI) {
+    const int64_t tiles = (n + RPB - 1) / RPB;
+    const int64_t tpb = (tiles + nb - 1) / nb;
+    tile0 = (int64_t)blockIdx.x * tpb;
+    tile1 = min(tiles, tile0 + tpb);
+  }
   const int g = blockIdx.y;
   const int col0 = g * COLS;
   const int ncol = min(COLS, a.m - col0);
-  const int64_t row_base = (int64_t)blockIdx.x * ((int64_t)LV_THREADS * VW * RPT);
   const int t = threadIdx.x;
   const int lane = t % kWave, wave = t / kWave;
   T* __restrict__ X = static_cast<T*>(a.X);
@@ -124,36 +137,39 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
   if (!STEP1 && a.uk_idx) ukp += (int64_t)(*a.uk_idx) * a.ldu_idx;
   const T* __restrict__ vnp = static_cast<const T*>(a.vnext);
   if (LOOKAHEAD && a.vn_idx) vnp += (int64_t)(*a.vn_idx) * a.ldv_idx;
-
-  int64_t rows[RPT], rowc[RPT];
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    rows[r] = row_base + ((int64_t)r * LV_THREADS + t) * VW;
-    rowc[r] = rows[r] < n ? rows[r] : 0;
-  }
-
-  // 1. Every load of the block first: the active columns (a column past the
-  //    last reads the last one and is not stored; the source of Step 1 may
-  //    be the destination itself), u_k and v_{k+1}.
-  T xv[COLS][RPT][VW];
   const T* __restrict__ src = STEP1 ? static_cast<const T*>(a.src) : X;
   const int64_t lds = STEP1 ? a.lds : a.ldx;
-#pragma unroll
-  for (int c = 0; c < COLS; ++c) {
-    const T* __restrict__ col = src + (int64_t)phys(min(col0 + c, a.m - 1)) * lds;
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) load_vec<T, VW>(col, rowc[r], xv[c][r]);
-  }
+
+  int64_t rows[RPT], rowc[RPT];
+  T xv[COLS][RPT][VW];
   T uv[RPT][VW], vv[RPT][VW];
+  // 1. Every load of a tile at once: the active columns (a column past the
+  //    last reads the last one and is not stored; the source of Step 1 may
+  //    be the destination itself), u_k and v_{k+1}.
+  auto load_tile = [&](int64_t tile) {
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    if constexpr (!STEP1) load_vec<T, VW>(ukp, rowc[r], uv[r]);
-    if constexpr (LOOKAHEAD) load_vec<T, VW>(vnp, rowc[r], vv[r]);
-  }
+    for (int r = 0; r < RPT; ++r) {
+      rows[r] = tile * RPB + ((int64_t)r * LV_THREADS + t) * VW;
+      rowc[r] = rows[r] < n ? rows[r] : 0;
+    }
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      const T* __restrict__ col = src + (int64_t)phys(min(col0 + c, a.m - 1)) * lds;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) load_vec<T, VW>(col, rowc[r], xv[c][r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      if constexpr (!STEP1) load_vec<T, VW>(ukp, rowc[r], uv[r]);
+      if constexpr (LOOKAHEAD) load_vec<T, VW>(vnp, rowc[r], vv[r]);
+    }
+  };
+  load_tile(tile0);
   __builtin_amdgcn_sched_barrier(0);
 
   // 2. Products c_q = v_k^T x_q of this block's columns (and of the pivot
-  //    column when forming gamma_k), from the previous launch's partials.
+  //    column when forming gamma_k), from the previous launch's partials,
+  //    once per block while the first tile's loads are in flight.
   __shared__ double cq_s[COLS];
   __shared__ double gam_s;
   if constexpr (!STEP1) {
@@ -169,10 +185,6 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
     }
     __syncthreads();
   }
-
-  // 3. Per-row factors: 1/r_i (Step 1) or h_k[i] = u_k[i] / gamma_k (level).
-  double hrow[RPT][VW];
-  double vn[RPT][VW];
   double inv_gamma = 0.0;
   if constexpr (!STEP1) {
     double gam;
@@ -187,43 +199,50 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
     }
     inv_gamma = 1.0 / gam;
   }
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const bool ok = rows[r] < n;
-    if constexpr (STEP1) {
-#pragma unroll
-      for (int e = 0; e < VW; ++e) {
-        const double rv = a.r ? a.r[rowc[r] + e] : 1.0;   // no r: Step 1 already applied (block R)
-        if (ok && (!(rv > 0.0) || !__builtin_isfinite(rv))) atomicOr(a.status, kStatusNotSpd);
-        hrow[r][e] = ok ? 1.0 / rv : 0.0;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < VW; ++e) hrow[r][e] = ok ? (double)uv[r][e] * inv_gamma : 0.0;
-    }
-    if constexpr (LOOKAHEAD) {
-#pragma unroll
-      for (int e = 0; e < VW; ++e) vn[r][e] = ok ? (double)vv[r][e] : 0.0;
-    }
-  }
-
-  // 4. Update, look-ahead products, stores.
   double acc[COLS];
 #pragma unroll
-  for (int c = 0; c < COLS; ++c) {
-    acc[c] = 0.0;
-    double cq = 0.0;
-    if constexpr (!STEP1) cq = (c < ncol) ? cq_s[c] : 0.0;
+  for (int c = 0; c < COLS; ++c) acc[c] = 0.0;
+  for (int64_t tile = tile0; tile < tile1; ++tile) {
+    if (tile != tile0) load_tile(tile);
+    // 3. Per-row factors: 1/r_i (Step 1) or h_k[i] = u_k[i] / gamma_k (level).
+    double hrow[RPT][VW];
+    double vn[RPT][VW];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
+      const bool ok = rows[r] < n;
+      if constexpr (STEP1) {
 #pragma unroll
-      for (int e = 0; e < VW; ++e) {
-        double x = (double)xv[c][r][e];
-        x = STEP1 ? x * hrow[r][e] : x - hrow[r][e] * cq;
-        xv[c][r][e] = (T)x;
-        if constexpr (LOOKAHEAD) acc[c] += vn[r][e] * (double)xv[c][r][e];
+        for (int e = 0; e < VW; ++e) {
+          const double rv = a.r ? a.r[rowc[r] + e] : 1.0;   // no r: Step 1 already applied (block R)
+          if (ok && (!(rv > 0.0) || !__builtin_isfinite(rv))) atomicOr(a.status, kStatusNotSpd);
+          hrow[r][e] = ok ? 1.0 / rv : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) hrow[r][e] = ok ? (double)uv[r][e] * inv_gamma : 0.0;
       }
-      if (c < ncol && rows[r] < n) store_vec<T, VW>(Out + (int64_t)phys(col0 + c) * ldo, rows[r], xv[c][r]);
+      if constexpr (LOOKAHEAD) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) vn[r][e] = ok ? (double)vv[r][e] : 0.0;
+      }
+    }
+
+    // 4. Update, look-ahead products, stores.
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      double cq = 0.0;
+      if constexpr (!STEP1) cq = (c < ncol) ? cq_s[c] : 0.0;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          double x = (double)xv[c][r][e];
+          x = STEP1 ? x * hrow[r][e] : x - hrow[r][e] * cq;
+          xv[c][r][e] = (T)x;
+          if constexpr (LOOKAHEAD) acc[c] += vn[r][e] * (double)xv[c][r][e];
+        }
+        if (c < ncol && rows[r] < n) store_vec<T, VW>(Out + (int64_t)phys(col0 + c) * ldo, rows[r], xv[c][r]);
+      }
     }
   }
   if constexpr (!LOOKAHEAD) return;
@@ -257,36 +276,46 @@ __global__ __launch_bounds__(kWave) void gamma_kernel(const double* __restrict__
   }
 }
 
-template <typename T, int VW>
-enkf_status launch_t(const LevelArgs& a, hipStream_t s) {
-  if (a.m <= 0) return ENKF_SUCCESS;
-  const int64_t rows_per_block = (int64_t)LV_THREADS * VW * LV_RPT;
-  const int64_t nb = (a.n + rows_per_block - 1) / rows_per_block;
-  const int ng = (a.m + LV_COLS - 1) / LV_COLS;
-  if (nb > 0x7fffffff || ng > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "level sweep: problem too large for grid");
-  dim3 grid((unsigned)nb, (unsigned)ng);
+template <typename T, int VW, bool MULTI>
+enkf_status launch_flags(const LevelArgs& a, dim3 grid, hipStream_t s) {
   const bool step1 = a.src != nullptr, look = a.vnext != nullptr, own = a.gamma_out != nullptr;
   if (step1) {
-    if (look) level_kernel<T, VW, true, true, false><<<grid, LV_THREADS, 0, s>>>(a);
-    else level_kernel<T, VW, true, false, false><<<grid, LV_THREADS, 0, s>>>(a);
+    if (look) level_kernel<T, VW, true, true, false, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
+    else level_kernel<T, VW, true, false, false, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
   } else if (own) {
-    if (look) level_kernel<T, VW, false, true, true><<<grid, LV_THREADS, 0, s>>>(a);
-    else level_kernel<T, VW, false, false, true><<<grid, LV_THREADS, 0, s>>>(a);
+    if (look) level_kernel<T, VW, false, true, true, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
+    else level_kernel<T, VW, false, false, true, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
   } else {
-    if (look) level_kernel<T, VW, false, true, false><<<grid, LV_THREADS, 0, s>>>(a);
-    else level_kernel<T, VW, false, false, false><<<grid, LV_THREADS, 0, s>>>(a);
+    if (look) level_kernel<T, VW, false, true, false, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
+    else level_kernel<T, VW, false, false, false, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
   }
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
+}
+
+template <typename T, int VW>
+enkf_status launch_t(const LevelArgs& a, hipStream_t s) {
+  if (a.m <= 0) return ENKF_SUCCESS;
+  const int64_t nb = level_row_blocks(ENKF_F64, VW, a.n);
+  const int ng = (a.m + LV_COLS - 1) / LV_COLS;
+  if (nb > 0x7fffffff || ng > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "level sweep: problem too large for grid");
+  const int64_t rpb = (int64_t)LV_THREADS * VW * LV_RPT;
+  if (nb < (a.n + rpb - 1) / rpb) return launch_flags<T, VW, true>(a, dim3((unsigned)nb, (unsigned)ng), s);
+  return launch_flags<T, VW, false>(a, dim3((unsigned)nb, (unsigned)ng), s);
 }
 
 }  // namespace
 
 int level_vw(enkf_dtype dt) { return dt == ENKF_F64 ? 2 : 4; }
 
+// Row blocks of a level launch: one tile of LV_THREADS*VW*LV_RPT rows each,
+// up to kLvMaxRowBlocks; past that a block walks several consecutive tiles,
+// so the previous launch's partials that every block sums stay few.
 int level_row_blocks(enkf_dtype, int vw, int64_t n) {
   const int64_t rpb = (int64_t)LV_THREADS * vw * LV_RPT;
-  return (int)((n + rpb - 1) / rpb);
+  const int64_t tiles = (n + rpb - 1) / rpb;
+  const int64_t tpb = (tiles + kLvMaxRowBlocks - 1) / kLvMaxRowBlocks;
+  return (int)((tiles + tpb - 1) / tpb);
 }
 
 enkf_status launch_level(enkf_dtype dt, const LevelArgs& a, hipStream_t s) {

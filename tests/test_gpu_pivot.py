@@ -39,7 +39,7 @@ def _check_order(r, V, D, g, perm):
 
 
 @pytest.mark.parametrize("n,N,nrhs", [(1, 1, 1), (7, 5, 3), (1000, 17, 17), (4099, 33, 5), (65536, 96, 96),
-                                      (3, 40, 40)])
+                                      (3, 40, 40), (600008, 9, 9)])
 def test_pivoted_solve_matches_oracle(n, N, nrhs):
     import torch
     print(f"pivot fp64 n={n} N={N} nrhs={nrhs}", flush=True)
