@@ -33,8 +33,11 @@ __device__ __forceinline__ mf_h8 cal_operand<MfmaF16>(int l) {
   return v;
 }
 
+// Two waves per SIMD at least: with the default budget (eight) the FP64
+// accumulators do not fit the VGPRs, and the compiler copies them to and from
+// the accumulation registers around every group of MFMAs.
 template <typename MF>
-__global__ __launch_bounds__(CAL_NT) void mfma_loop_kernel(int iters, float* __restrict__ out) {
+__global__ __launch_bounds__(CAL_NT, 2) void mfma_loop_kernel(int iters, float* __restrict__ out) {
   const int l = threadIdx.x % kWave;
   const typename MF::op_t a = cal_operand<MF>(l), b = cal_operand<MF>(l + 3);
   typename MF::acc_t acc[CAL_ACC];
