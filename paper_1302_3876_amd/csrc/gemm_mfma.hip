@@ -289,12 +289,12 @@ __global__ __launch_bounds__(256) void convert_b_kernel(int K, int m, const doub
 // 16-byte LDS writes along rows/columns, conflict-free MFMA operand reads.
 // Waves 2 x 2: wave (w/2, w%2) owns TC/2 columns x TR/2 rows. One LDS
 // buffer; the next stage is prefetched into registers.
-// FP64: a budget of two waves per SIMD lets the compiler keep the
-// accumulators in VGPRs; with the default one it moved them to and from the
-// accumulation registers around every stage's MFMAs (and needed more
-// registers in all).
+// A budget of two waves per SIMD lets the compiler keep the accumulators in
+// VGPRs; with the default one it split them from the MFMA operands into the
+// accumulation registers (FP64: copied in and out around every stage's
+// MFMAs) and needed more registers in all, so fewer waves fit.
 template <typename T, int MODE, int TR, int TC, bool VEC, bool LOOP>
-__global__ __launch_bounds__(NT, sizeof(T) == 8 ? 2 : 1) void nn_kernel(NnArgs p, const T* __restrict__ Bt, int ldbc) {
+__global__ __launch_bounds__(NT, 2) void nn_kernel(NnArgs p, const T* __restrict__ Bt, int ldbc) {
   static_assert(!LOOP || MODE == NN_ANALYSIS, "only ANALYSIS walks the column tiles");
   typedef typename MfOf<T>::type MF;
   typedef typename V16<T>::type vt;
