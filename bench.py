@@ -392,7 +392,8 @@ def run_cycle(args, pk, torch):
     out = {}
     for algo in ("plain", "blocked"):
         XB = dev(XB0)
-        gen = pk.cycle_l96(XB, obs_d, ys_d, Es_d, r_d, c["nsteps"], algo=algo)
+        gen = pk.cycle_l96(XB, obs_d, ys_d, Es_d, r_d, c["nsteps"], algo=algo,
+                           block=args.block if algo == "blocked" else 0)
         rf, ra, times = [], [], []
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(c["cycles"] + 1)]
         torch.cuda.synchronize()
@@ -414,11 +415,11 @@ def run_cycle(args, pk, torch):
         print(f"[bench] cycle {algo}: {np.mean(steady):.3f} ms/cycle, RMSE a {rmse_a[-1]:.5f}", file=sys.stderr,
               flush=True)
     if not args.no_cycle_shapes:
-        out["cycle_shapes"] = run_cycle_shapes(pk, torch)
+        out["cycle_shapes"] = run_cycle_shapes(pk, torch, args.block)
     return out, (XB0, obs, r, truths, ys, Es)
 
 
-def run_cycle_shapes(pk, torch):
+def run_cycle_shapes(pk, torch, block=0):
     """The cycling filter at other (n_state = n_obs, N) shapes of the paper's
     Lorenz-96 range, plain and blocked: milliseconds per cycle over all but the
     first cycle, and the last forecast and analysis RMSE against the truth.
@@ -441,7 +442,9 @@ def run_cycle_shapes(pk, torch):
             torch.cuda.synchronize()
             ev[0].record()
             rf, ra = [], []
-            for k, (fmean, amean) in enumerate(pk.cycle_l96(XB, obs_d, ys_d, Es_d, r_d, c["nsteps"], algo=algo)):
+            blk = block if algo == "blocked" else 0
+            for k, (fmean, amean) in enumerate(pk.cycle_l96(XB, obs_d, ys_d, Es_d, r_d, c["nsteps"], algo=algo,
+                                                            block=blk)):
                 ev[k + 1].record()
                 rf.append(fmean)
                 ra.append(amean)

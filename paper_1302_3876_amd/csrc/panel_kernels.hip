@@ -37,8 +37,11 @@ __device__ __forceinline__ double recip(double x) {
   return r;
 }
 
-// One block of 256 threads as a 16 x 16 grid; thread (ti, tj) keeps the
-// elements (i, j) = (ti + 16 r, tj + 16 c), r, c < 8, of the symmetrised
+constexpr int PF_TI = 32, PF_TJ = 16;  // thread grid: rows x columns
+constexpr int PF_NT = PF_TI * PF_TJ;    // 512 threads: 8 waves, two per SIMD
+
+// One block of 512 threads as a 32 x 16 grid; thread (ti, tj) keeps the
+// elements (i, j) = (ti + 32 r, tj + 16 c), r < 4, c < 8, of the symmetrised
 // M = I + (P_K + P_K^T)/2 (padded with identity rows to a multiple of 4) in
 // registers. M is inverted in place by block sweeps on four pivots at a time
 // (Gauss-Jordan elimination in the natural order without pivoting, which M
@@ -52,33 +55,37 @@ __device__ __forceinline__ double recip(double x) {
 // k0..k0+3 (Section 3.3). After all sweeps the registers hold -M^{-1}. The
 // next four columns are published through the LDS (double-buffered: one
 // barrier per four levels).
-__global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* __restrict__ P, int64_t ldp,
-                                                           double* __restrict__ gamma_out, double* __restrict__ Minv,
-                                                           unsigned* status) {
+__global__ __launch_bounds__(PF_NT) void panel_factor_kernel(int b, const double* __restrict__ P, int64_t ldp,
+                                                             double* __restrict__ gamma_out, double* __restrict__ Minv,
+                                                             unsigned* status) {
   constexpr int MP = kMaxPanel;
+  constexpr int RR = MP / PF_TI, CC = MP / PF_TJ;  // rows and columns per thread
+  constexpr int SUB = PF_TJ / 4;                   // four-pivot steps per column group
+  static_assert(SUB % 2 == 0 && PF_TI % PF_TJ == 0, "buffers alternate within a group; a group's rows in one row group");
   __shared__ double pan[2][4 * MP];
-  const int t = threadIdx.x, ti = t % 16, tj = t / 16;
+  const int t = threadIdx.x, ti = t % PF_TI, tj = t / PF_TI;
   const int b4 = (b + 3) / 4 * 4;
-  double a[8][8];
+  double a[RR][CC];
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+  for (int r = 0; r < RR; ++r)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int i = ti + 16 * r, j = tj + 16 * c;
+    for (int c = 0; c < CC; ++c) {
+      const int i = ti + PF_TI * r, j = tj + PF_TJ * c;
       const int ic = min(i, b - 1), jc = min(j, b - 1);
       const double x = P[ic + (int64_t)jc * ldp], y = P[jc + (int64_t)ic * ldp];
       a[r][c] = (i < b && j < b) ? (i == j ? 1.0 : 0.0) + 0.5 * (x + y) : (i == j && i < b4 ? 1.0 : 0.0);
     }
   if (tj < 4)                                      // columns 0..3
 #pragma unroll
-    for (int r = 0; r < 8; ++r) pan[0][tj * MP + ti + 16 * r] = a[r][0];
+    for (int r = 0; r < RR; ++r) pan[0][tj * MP + ti + PF_TI * r] = a[r][0];
   __syncthreads();
   auto phase = [&](auto kb_c) {
-    constexpr int KB = decltype(kb_c)::value;
-    if (16 * KB >= b4) return;
+    constexpr int KB = decltype(kb_c)::value;      // column group of the pivots
+    constexpr int RK = KB * PF_TJ / PF_TI;         // row group of the pivots
+    if (PF_TJ * KB >= b4) return;
 #pragma unroll 1
-    for (int ss = 0; ss < 4; ++ss) {
-      const int k0 = 16 * KB + 4 * ss;
+    for (int ss = 0; ss < SUB; ++ss) {
+      const int k0 = PF_TJ * KB + 4 * ss;
       if (k0 >= b4) break;
       const double* Pc = pan[ss & 1];
       double* Pn = pan[(ss + 1) & 1];
@@ -133,37 +140,37 @@ __global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* 
             if (!(dv[q] > 0.0) || !__builtin_isfinite(dv[q])) atomicOr(status, kStatusNotSpd);
           }
       // rows: g_i = A_iK W
-      double g[8][4];
+      double g[RR][4];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
+      for (int r = 0; r < RR; ++r) {
         double x[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) x[q] = Pc[q * MP + ti + 16 * r];
+        for (int q = 0; q < 4; ++q) x[q] = Pc[q * MP + ti + PF_TI * r];
 #pragma unroll
         for (int v = 0; v < 4; ++v) g[r][v] = fma(x[3], W[3][v], fma(x[2], W[2][v], fma(x[1], W[1][v], x[0] * W[0][v])));
       }
-      const int pi = ti - k0 % 16, pj = tj - k0 % 16;
+      const int pi = ti - k0 % PF_TI, pj = tj - k0 % PF_TJ;
       const bool rowK = pi >= 0 && pi < 4, colK = pj >= 0 && pj < 4;
       // every element: A_ij -= g_i . A_jK; rows of K: (W A_Kj)_pi
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
+      for (int c = 0; c < CC; ++c) {
         double h[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) h[q] = Pc[q * MP + tj + 16 * c];
+        for (int q = 0; q < 4; ++q) h[q] = Pc[q * MP + tj + PF_TJ * c];
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
+        for (int r = 0; r < RR; ++r)
           a[r][c] = fma(-g[r][3], h[3], fma(-g[r][2], h[2], fma(-g[r][1], h[1], fma(-g[r][0], h[0], a[r][c]))));
         if (rowK) {
           double x = 0.0;
 #pragma unroll
           for (int q = 0; q < 4; ++q)
             if (q == pi) x = ((W[q][0] * h[0] + W[q][1] * h[1]) + W[q][2] * h[2]) + W[q][3] * h[3];
-          a[KB][c] = x;
+          a[RK][c] = x;
         }
       }
       if (colK) {                                  // columns of K: (A_iK W)_pj; the K x K block: -W
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < RR; ++r) {
           double x = 0.0;
 #pragma unroll
           for (int q = 0; q < 4; ++q)
@@ -177,20 +184,20 @@ __global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* 
 #pragma unroll
             for (int v = 0; v < 4; ++v)
               if (q == pi && v == pj) x = -W[q][v];
-          a[KB][KB] = x;
+          a[RK][KB] = x;
         }
       }
       // the next four columns
       const int kn = k0 + 4;
-      const int qn = tj - kn % 16;
+      const int qn = tj - kn % PF_TJ;
       if (kn < b4 && qn >= 0 && qn < 4) {
-        if (ss < 3) {
+        if (ss < SUB - 1) {
 #pragma unroll
-          for (int r = 0; r < 8; ++r) Pn[qn * MP + ti + 16 * r] = a[r][KB];
+          for (int r = 0; r < RR; ++r) Pn[qn * MP + ti + PF_TI * r] = a[r][KB];
         } else {
-          if constexpr (KB < 7) {
+          if constexpr (KB < CC - 1) {
 #pragma unroll
-            for (int r = 0; r < 8; ++r) Pn[qn * MP + ti + 16 * r] = a[r][KB + 1];
+            for (int r = 0; r < RR; ++r) Pn[qn * MP + ti + PF_TI * r] = a[r][KB + 1];
           }
         }
       }
@@ -206,10 +213,10 @@ __global__ __launch_bounds__(256) void panel_factor_kernel(int b, const double* 
   phase(std::integral_constant<int, 6>{});
   phase(std::integral_constant<int, 7>{});
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+  for (int r = 0; r < RR; ++r)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int i = ti + 16 * r, j = tj + 16 * c;
+    for (int c = 0; c < CC; ++c) {
+      const int i = ti + PF_TI * r, j = tj + PF_TJ * c;
       if (i < b && j < b) Minv[i + (int64_t)j * b] = -a[r][c];
     }
 }
@@ -391,7 +398,7 @@ enkf_status launch_scale_rows(enkf_dtype dt, int64_t n, int m, const void* X, in
 enkf_status launch_panel_factor(int b, const double* P, int64_t ldp, double* gamma_out, double* Minv, unsigned* status,
                                 hipStream_t s) {
   if (b < 1 || b > kMaxPanel) return fail(ENKF_ERR_NOT_SUPPORTED, "panel width outside [1, 128]");
-  panel_factor_kernel<<<1, 256, 0, s>>>(b, P, ldp, gamma_out, Minv, status);
+  panel_factor_kernel<<<1, PF_NT, 0, s>>>(b, P, ldp, gamma_out, Minv, status);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
