@@ -29,8 +29,10 @@ template <typename T> struct LzMf;
 template <> struct LzMf<double> { typedef MfmaF64 type; static constexpr int KC = 16; };
 template <> struct LzMf<float> { typedef MfmaF32 type; static constexpr int KC = 32; };
 
+// Two waves per SIMD at least (the LDS allows no more): the accumulators then
+// stay in VGPRs instead of being split off into accumulation registers.
 template <typename T>
-__global__ __launch_bounds__(LZ_NT) void localize_kernel(LocalizeArgs p) {
+__global__ __launch_bounds__(LZ_NT, 2) void localize_kernel(LocalizeArgs p) {
   typedef typename LzMf<T>::type MF;
   constexpr int KC = LzMf<T>::KC;
   constexpr int LDS_ROW = LZ_TI + 16;   // [k][state row] stages
