@@ -581,7 +581,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the analysis path is built and timed on a single MI355X; "
-              "sharding across GPUs is described in DESIGN.md but not built. Run with --gpus 1.", file=sys.stderr)
+              "sharding it across GPUs is not built. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
 
