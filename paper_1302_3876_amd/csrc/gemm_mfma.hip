@@ -657,12 +657,18 @@ enkf_status analysis_small(NnArgs p, const T* Bt, int ldbc, hipStream_t s) {
 }
 
 constexpr int64_t kTnTargetBlocks = 768;   // ~3 blocks per CU
-constexpr int64_t kTnMinRows = 256;
+constexpr int64_t kTnMinRows = 64;
 
+// Row chunks of a split-K product: enough blocks to fill the part, at least
+// kTnMinRows rows each, and no more partials (chunks x a x m, FP64) than
+// about twice the operands' elements (n x (a + m)), so that for short,
+// wide products the partial sums do not outweigh the product.
 int64_t tn_chunks(int64_t n, int a, int m) {
   const int64_t tiles = (int64_t)((a + TILE - 1) / TILE) * ((m + TILE - 1) / TILE);
   int64_t chunks = (kTnTargetBlocks + tiles - 1) / tiles;
-  const int64_t max_chunks = (n + kTnMinRows - 1) / kTnMinRows;
+  const int64_t max_rows = (n + kTnMinRows - 1) / kTnMinRows;
+  const int64_t max_partials = std::max<int64_t>(4, 2 * n * ((int64_t)a + m) / ((int64_t)a * m));
+  const int64_t max_chunks = std::min(max_rows, max_partials);
   if (chunks > max_chunks) chunks = max_chunks;
   if (chunks < 1) chunks = 1;
   return chunks;
