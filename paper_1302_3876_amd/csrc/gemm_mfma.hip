@@ -798,7 +798,9 @@ enkf_status nn_typed(int mode, NnArgs p, hipStream_t s) {
       return analysis_small<T>(p, Bt, ldbc, s);
     return nn_pick<T, NN_ANALYSIS>(p, Bt, ldbc, vec, s);
   }
-  return nn_pick<T, NN_RESIDUAL>(p, Bt, ldbc, vec, s);
+  // the refinement residual is formed in FP64 only
+  if constexpr (sizeof(T) == 8) return nn_pick<T, NN_RESIDUAL>(p, Bt, ldbc, vec, s);
+  else return fail(ENKF_ERR_NOT_SUPPORTED, "residual product: FP64 only");
 }
 
 }  // namespace

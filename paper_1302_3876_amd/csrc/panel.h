@@ -26,10 +26,9 @@ enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float
 enkf_status launch_add(int64_t n, int m, const double* X, int64_t ldx, double* Z, int64_t ldz, hipStream_t s);
 enkf_status launch_widen(int64_t n, int m, const float* W, int64_t ldw, double* Z, int64_t ldz, bool accumulate,
                          const double* sumsq, hipStream_t s);
-// out[0] = ||X||_F^2 and, when Y is given, out[1] = ||Y||_F^2 (out[1] is
-// left alone otherwise); fixed-order two-stage sums.
+// out[0] = ||X||_F^2 (fixed-order two-stage sum; part holds
+// norm_partial_elems() doubles).
 int norm_partial_elems();
-enkf_status launch_sumsq2(int64_t n, int m, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* part,
-                          double* out, hipStream_t s);
+enkf_status launch_sumsq(int64_t n, int m, const double* X, int64_t ldx, double* part, double* out, hipStream_t s);
 
 }  // namespace enkf

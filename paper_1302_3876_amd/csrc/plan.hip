@@ -779,7 +779,7 @@ enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z
   }
   // ||D||^2, constant over the solve
   if (!d_norm) return ENKF_SUCCESS;
-  return launch_sumsq2(n, nrhs, static_cast<const double*>(D), ldd, nullptr, 0, norms + 2, norms + 1, stream);
+  return launch_sumsq(n, nrhs, static_cast<const double*>(D), ldd, norms + 2, norms + 1, stream);
 }
 
 // ------------------------------------------------------------------ common
