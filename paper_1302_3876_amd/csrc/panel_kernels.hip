@@ -303,53 +303,36 @@ __global__ __launch_bounds__(256) void add_kernel(int64_t n, int m, const double
 
 constexpr int NORM_BLOCKS = 1024;
 
-// Per-block partial sums of squares of one or two (Y != NULL) n x m FP64
-// matrices, in a fixed order; then one block sums the partials.
+// Per-block partial sums of squares of an n x m FP64 matrix, in a fixed
+// order; then one block sums the partials.
 __global__ __launch_bounds__(256) void sumsq_partial_kernel(int64_t n, int m, const double* __restrict__ X, int64_t ldx,
-                                                            const double* __restrict__ Y, int64_t ldy,
                                                             double* __restrict__ part) {
-  __shared__ double red[2][4];
+  __shared__ double red[4];
   const int64_t total = n * (int64_t)m;
-  double sx = 0.0, sy = 0.0;
+  double sx = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     const int64_t i = e % n, j = e / n;
     const double x = X[i + j * ldx];
     sx += x * x;
-    if (Y) {
-      const double y = Y[i + j * ldy];
-      sy += y * y;
-    }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    sx += __shfl_xor(sx, off, 64);
-    sy += __shfl_xor(sy, off, 64);
-  }
+  for (int off = 32; off > 0; off >>= 1) sx += __shfl_xor(sx, off, 64);
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  if (lane == 0) { red[0][w] = sx; red[1][w] = sy; }
+  if (lane == 0) red[w] = sx;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
-    part[2 * blockIdx.x + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
-  }
+  if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-__global__ __launch_bounds__(64) void sumsq_final_kernel(int nblk, int two, const double* __restrict__ part,
+__global__ __launch_bounds__(64) void sumsq_final_kernel(int nblk, const double* __restrict__ part,
                                                          double* __restrict__ out) {
-  double sx = 0.0, sy = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) { sx += part[2 * b]; sy += part[2 * b + 1]; }
-  for (int off = 32; off > 0; off >>= 1) {
-    sx += __shfl_xor(sx, off, 64);
-    sy += __shfl_xor(sy, off, 64);
-  }
-  if (threadIdx.x == 0) {
-    out[0] = sx;
-    if (two) out[1] = sy;
-  }
+  double sx = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) sx += part[b];
+  for (int off = 32; off > 0; off >>= 1) sx += __shfl_xor(sx, off, 64);
+  if (threadIdx.x == 0) out[0] = sx;
 }
 
 }  // namespace
 
-int norm_partial_elems() { return 2 * NORM_BLOCKS; }
+int norm_partial_elems() { return NORM_BLOCKS; }
 
 enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float* Y, int64_t ldy, const double* sumsq,
                            const double* r, unsigned* status, hipStream_t s) {
@@ -370,15 +353,14 @@ enkf_status launch_widen(int64_t n, int m, const float* W, int64_t ldw, double* 
   return ENKF_SUCCESS;
 }
 
-enkf_status launch_sumsq2(int64_t n, int m, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* part,
-                          double* out, hipStream_t s) {
+enkf_status launch_sumsq(int64_t n, int m, const double* X, int64_t ldx, double* part, double* out, hipStream_t s) {
   const int64_t total = n * (int64_t)m;
   int nblk = (int)((total + 255) / 256);
   if (nblk > NORM_BLOCKS) nblk = NORM_BLOCKS;
   if (nblk < 1) nblk = 1;
-  sumsq_partial_kernel<<<nblk, 256, 0, s>>>(n, m, X, ldx, Y, ldy, part);
+  sumsq_partial_kernel<<<nblk, 256, 0, s>>>(n, m, X, ldx, part);
   ENKF_HIP_CHECK(hipGetLastError());
-  sumsq_final_kernel<<<1, 64, 0, s>>>(nblk, Y ? 1 : 0, part, out);
+  sumsq_final_kernel<<<1, 64, 0, s>>>(nblk, part, out);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
