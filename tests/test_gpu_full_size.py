@@ -102,3 +102,65 @@ def test_c5_ensemble_shape():
     ref = oracle.analysis(XB32[rows], V, Zh)
     inc, inco = XA[rows] - XB32[rows], ref - XB32[rows]
     assert np.max(np.abs(inc - inco)) <= 2e-5 * np.max(np.abs(inco))
+
+
+def test_c5_full_size_sampled():
+    """The c5 configuration at its full size (n_state = 2,097,152, N = 1024,
+    n_obs = 524,288; FP32 ensemble) in the launch configuration bench.py
+    times (panels of 128 levels, FP32 panels refining the FP64 system to
+    1e-10, the FP32 analysis product), checked on samples: the build on 512
+    observation rows against the oracle; the solve by its FP64 residual on
+    32 columns (formed on the host with numpy) and its first eight pivots
+    against the oracle's level iteration on V's first columns; the analysis
+    increment on 256 state rows against S_rows (V^T Z) with the N x N factor
+    formed on the host in FP64 (a plain matrix product: the oracle's own
+    loops would need minutes for it). Bounds: build and pivots as in the
+    smaller c5 test; sampled residual 1e-9 (the device's whole-matrix gate is
+    1e-10); increment 2e-5 of its largest entry (FP32 storage and products)."""
+    import torch
+    import paper_1302_3876_amd as pk
+    print("c5 full size", flush=True)
+    w = synth.c5()
+    n, N = w.n_obs, w.n_ens
+    f32 = torch.float32
+    g = np.random.default_rng(55)
+    XBd = pk.to_colmajor(w.XB.astype(np.float32), dtype=f32)
+    Ed = pk.to_colmajor(w.E.astype(np.float32), dtype=f32)
+    V32, D32 = pk.colmajor(n, N, f32), pk.colmajor(n, N, f32)
+    pk.enkf_build_vd(XBd, dev(w.obs_idx), dev(w.y), Ed, V32, D32)
+    torch.cuda.synchronize()
+    V, D = host(V32), host(D32)
+    orows = np.sort(g.choice(n, 512, replace=False))
+    XBs = w.XB[w.obs_idx[orows]].astype(np.float32).astype(np.float64)
+    Es = w.E[orows].astype(np.float32).astype(np.float64)
+    Vo, Do = oracle.build_vd(XBs, np.arange(len(orows), dtype=np.int64), w.y[orows], Es)
+    assert np.max(np.abs(V[orows] - Vo)) <= 4 * 2.0 ** -24 * np.max(np.abs(Vo)) + 4 * N * 2.0 ** -52 * np.max(np.abs(XBs))
+    assert np.max(np.abs(D[orows] - Do)) <= 4 * 2.0 ** -24 * np.max(np.abs(Do))
+    del Ed, XBs, Es
+    plan = pk.Plan(dev(w.r), dev(V), algo="blocked", math="f32", block=128, refine_max_iter=10, refine_tol=1e-10)
+    Z, info = plan.solve(dev(D), info=True)
+    XA = plan.analysis_ex(XBd, Z, math="f32")
+    torch.cuda.synchronize()
+    gam, _ = plan.pivots()
+    Zh = host(Z)
+    del Z
+    plan.close()
+    print({"info": info}, flush=True)
+    assert info["rel_residual"] <= 1e-10
+    cols = np.sort(g.choice(N, 32, replace=False))
+    Zc = Zh[:, cols]
+    rho = D[:, cols] - w.r[:, None] * Zc - V @ (V.T @ Zc)
+    rr = float(np.linalg.norm(rho) / np.linalg.norm(D[:, cols]))
+    print({"sampled_rel_residual": rr}, flush=True)
+    assert rr <= 1e-9
+    g8 = oracle.sm_solve(w.r, np.ascontiguousarray(V[:, :8]), np.ascontiguousarray(D[:, :1]))["gamma"]
+    assert np.allclose(gam[:8], g8, rtol=1e-5, atol=0)
+    G = V.T @ Zh / np.sqrt(N - 1)
+    del Zh, V, D
+    srows = np.sort(g.choice(w.n_state, 256, replace=False))
+    XBr = w.XB[srows].astype(np.float32).astype(np.float64)
+    ref = (XBr - XBr.mean(axis=1, keepdims=True)) @ G
+    inc = host(XA[torch.as_tensor(srows, device=XA.device)]) - XBr
+    err = float(np.max(np.abs(inc - ref)))
+    print({"increment_err": err, "scale": float(np.max(np.abs(ref)))}, flush=True)
+    assert err <= 2e-5 * np.max(np.abs(ref))
