@@ -442,35 +442,42 @@ __global__ __launch_bounds__(NT, 2) void nn_kernel(NnArgs p, const T* __restrict
   const T* __restrict__ Din = static_cast<const T*>(p.Din);
   T* __restrict__ Cout = static_cast<T*>(p.Cout);
   double ss = 0.0;   // RESIDUAL: this thread's sum of the stored rho^2
+  // RESIDUAL loads two inputs per output: its rows go in two halves, so the
+  // prefetched inputs leave registers for a third wave per SIMD
+  constexpr int JG = MODE == NN_RESIDUAL && RJ % 2 == 0 ? RJ / 2 : RJ;
 #pragma unroll
   for (int i = 0; i < CI; ++i) {
-    T cin[RJ][4], din[RJ][4];
-    double rr[RJ];
 #pragma unroll
-    for (int j = 0; j < RJ; ++j) {
+  for (int jg = 0; jg < RJ; jg += JG) {
+    T cin[JG][4], din[JG][4];
+    double rr[JG];
+#pragma unroll
+    for (int jj = 0; jj < JG; ++jj) {
+      const int j = jg + jj;
       const int64_t row = min(row0 + r_off + 16 * j + l % 16, rlim - 1);
-      if constexpr (MODE == NN_RESIDUAL) rr[j] = p.r[row];
+      if constexpr (MODE == NN_RESIDUAL) rr[jj] = p.r[row];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = min(col0 + c_off + 16 * i + MF::row(l, r), p.m - 1);
-        cin[j][r] = Cin[row + (int64_t)col * p.ldc];
-        if constexpr (MODE == NN_RESIDUAL) din[j][r] = Din[row + (int64_t)col * p.ldd];
+        cin[jj][r] = Cin[row + (int64_t)col * p.ldc];
+        if constexpr (MODE == NN_RESIDUAL) din[jj][r] = Din[row + (int64_t)col * p.ldd];
       }
     }
 #pragma unroll
-    for (int j = 0; j < RJ; ++j) {
+    for (int jj = 0; jj < JG; ++jj) {
+      const int j = jg + jj;
       double rinv = 1.0;
-      if constexpr (MODE == NN_RESIDUAL) rinv = 1.0 / rr[j];
+      if constexpr (MODE == NN_RESIDUAL) rinv = 1.0 / rr[jj];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int col = col0 + c_off + 16 * i + MF::row(l, r);
         const int64_t row = row0 + r_off + 16 * j + l % 16;
         const double prod = (double)acc[i][j][r];
-        const double c = (double)cin[j][r];
+        const double c = (double)cin[jj][r];
         double out;
         if constexpr (MODE == NN_UPDATE) out = c - prod;
         else if constexpr (MODE == NN_ANALYSIS) out = c + prod;
-        else out = (double)din[j][r] - (rr[j] * c + prod);
+        else out = (double)din[jj][r] - (rr[jj] * c + prod);
         const bool in = col < p.m && row < p.n;
         if constexpr (MODE == NN_RESIDUAL) {
           // the right-hand side of the next low-precision solve, Step 1
@@ -485,6 +492,7 @@ __global__ __launch_bounds__(NT, 2) void nn_kernel(NnArgs p, const T* __restrict
         }
       }
     }
+  }
   }
   if constexpr (MODE == NN_RESIDUAL) {
     // the block's share of ||rho||^2: lanes, then the 4 waves, in a fixed order
