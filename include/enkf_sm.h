@@ -19,8 +19,11 @@
  *     Every call only enqueues work on that stream and returns; nothing is
  *     synchronised unless the argument list says so.
  *   - The caller owns every buffer it passes. A plan borrows the r and V
- *     pointers given to enkf_sm_init: they must stay valid and unchanged until
- *     enkf_sm_destroy. A plan owns its workspace (allocated in enkf_sm_init).
+ *     pointers given to enkf_sm_init (or the last refactor): they must stay
+ *     valid and unchanged until enkf_sm_destroy, since the solves, the FP64
+ *     refinement residuals and the analysis read them again. (A copy would
+ *     double V's footprint: 4 GiB in FP64 at n = 2^21, N = 256.) A plan owns
+ *     its workspace (allocated in enkf_sm_init).
  *   - Every call returns an enkf_status. Argument errors are found on the host
  *     before anything is launched. Errors found by kernels (a pivot gamma_k not
  *     finite or not > 0, an r_i not finite or not > 0) are latched in a device
@@ -62,8 +65,12 @@ typedef enum { ENKF_SM_PLAIN = 0, ENKF_SM_BLOCKED = 1 } enkf_sm_algo;
  * cores. A type narrower than `dtype` makes the solve mixed precision: the
  * plan keeps an FP32 copy of V and of the factor, the panel products run in
  * `math`, the b x b panel pivots stay FP64, and enkf_sm_solve refines Z with
- * FP64 residuals D - (R Z + V (V^T Z)). The X2/X3 forms split each FP32
- * operand into a high and a low 16-bit part and sum the cross products. */
+ * FP64 residuals D - (R Z + V (V^T Z)). The split forms carry more of each
+ * FP32 operand: BF16X3 writes it as the sum of three BF16 parts (8 bits of
+ * significand each) and sums the six cross products of significance at
+ * least 2^-16 relative to the leading one; F16X2 writes it as an FP16 high
+ * part plus an FP16 low part stored scaled by 2^11 (11 bits each) and sums
+ * three cross products. Accumulation is FP32 in every form. */
 typedef enum {
     ENKF_MATH_F64 = 0,
     ENKF_MATH_F32 = 1,
@@ -76,6 +83,16 @@ typedef enum {
 /* Pivoting of Section 3.4 (eq. gamma-value): before level k the remaining
  * column with the largest gamma is swapped into position k. Plain only. */
 #define ENKF_FLAG_PIVOT 0x1u
+/* Diagnostics (FP64 storage, diagonal R, n_ens <= 4096; ignored otherwise):
+ * every synchronous solve (info != NULL) reports the relative residual and
+ * the normwise backward error of its Z,
+ *   eta = ||D - W Z||_F / (||W||_2 ||Z||_F + ||D||_F),
+ * with ||W||_2 estimated per factorisation as max r + the Rayleigh quotient
+ * of V^T V after 60 power steps (at most 2 ||W||_2; the N x N Gram costs
+ * 2 n N^2 flops). Plain and unrefined blocked solves form one FP64
+ * residual D - (R Z + V (V^T Z)) for it; an in-place solve (Z overwrote D)
+ * reports -1. */
+#define ENKF_FLAG_DIAGNOSE 0x2u
 
 typedef struct {
     int64_t n_obs;          /* n >= 1 */
@@ -94,10 +111,13 @@ typedef struct {
 
 typedef struct {
     int32_t refine_iters;   /* refinement steps taken by the last solve */
-    double rel_residual;    /* ||D - W Z||_F / ||D||_F of the last solve (mixed, or when computed) */
+    double rel_residual;    /* ||D - W Z||_F / ||D||_F of the last solve (refined or mixed solves, and
+                               every solve with ENKF_FLAG_DIAGNOSE), else -1 */
+    double backward_error;  /* eta of the last synchronous solve with ENKF_FLAG_DIAGNOSE, else -1 */
     double gamma_min;       /* smallest and largest pivot gamma_k of the factor */
     double gamma_max;
     int32_t device_status;  /* enkf_status latched by kernels (0 = none) */
+    int32_t hip_error;      /* hipPeekAtLastError() of the calling thread when the info was taken (0 = none) */
 } enkf_sm_info;
 
 typedef struct enkf_sm_plan_s* enkf_sm_plan;
@@ -180,7 +200,10 @@ enkf_status enkf_sm_refactor_block_r(enkf_sm_plan plan, const double* R_blocks, 
  * The D-dependent half of S*: Step 1 for D (Z0 = R^{-1} D) and the Z-updates
  * of every level (eq. SM-step-2-Z): Z = (R + V V^T)^{-1} D.
  * D and Z are n_obs x nrhs (nrhs >= 0; the analysis has nrhs = N) in the
- * plan's dtype; Z may alias D only if ldz == ldd. Allocates nothing.
+ * plan's dtype. The plain and the unrefined blocked solves may run in place
+ * (Z == D with ldz == ldd); refined and mixed-precision solves read D again
+ * for every residual and take no overlap of Z and D. Any other overlap is
+ * ENKF_ERR_INVALID_ARG. Allocates nothing.
  * info == NULL: asynchronous, refinement (if any) runs exactly
  *   refine_max_iter steps. info != NULL: synchronises the plan's stream,
  *   stops refinement at refine_tol, fills *info and returns latched errors.

@@ -26,6 +26,7 @@ ENKF_F64, ENKF_F32 = 0, 1
 ENKF_SM_PLAIN, ENKF_SM_BLOCKED = 0, 1
 MATH = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4, "f16x2": 5}
 ENKF_FLAG_PIVOT = 0x1
+ENKF_FLAG_DIAGNOSE = 0x2
 STATUS = {0: "ENKF_SUCCESS", 1: "ENKF_ERR_INVALID_ARG", 2: "ENKF_ERR_NOT_SPD", 3: "ENKF_ERR_NO_CONVERGENCE",
           4: "ENKF_ERR_HIP", 5: "ENKF_ERR_OUT_OF_MEMORY", 6: "ENKF_ERR_NOT_SUPPORTED"}
 KERNEL_CLASSES = {"factor_sweep": 0, "solve_sweep": 1, "build": 2, "analysis": 3, "gram": 4,
@@ -53,8 +54,8 @@ class LocalDesc(ctypes.Structure):
 
 class SmInfo(ctypes.Structure):
     _fields_ = [("refine_iters", ctypes.c_int32), ("rel_residual", ctypes.c_double),
-                ("gamma_min", ctypes.c_double), ("gamma_max", ctypes.c_double),
-                ("device_status", ctypes.c_int32)]
+                ("backward_error", ctypes.c_double), ("gamma_min", ctypes.c_double), ("gamma_max", ctypes.c_double),
+                ("device_status", ctypes.c_int32), ("hip_error", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -226,7 +227,8 @@ class Plan:
     ignored (enkf_sm_init_block_r)."""
 
     def __init__(self, r, V, algo: str = "plain", math: Optional[str] = None, block: int = 0, max_nrhs: int = 0,
-                 refine_max_iter: int = 0, refine_tol: float = 0.0, pivot: bool = False, block_r=None):
+                 refine_max_iter: int = 0, refine_tol: float = 0.0, pivot: bool = False, block_r=None,
+                 diagnose: bool = False):
         torch = _torch()
         self.dtype = _dtype_code(V)
         if math is None:
@@ -234,7 +236,8 @@ class Plan:
         pV, ldv = _mat(V, "V", self.dtype)
         n, N = V.shape
         self.desc = SmDesc(n, N, self.dtype, ENKF_SM_PLAIN if algo == "plain" else ENKF_SM_BLOCKED, MATH[math],
-                           block, max_nrhs, refine_max_iter, refine_tol, ENKF_FLAG_PIVOT if pivot else 0)
+                           block, max_nrhs, refine_max_iter, refine_tol,
+                           (ENKF_FLAG_PIVOT if pivot else 0) | (ENKF_FLAG_DIAGNOSE if diagnose else 0))
         self._r, self._V = r, V  # borrowed by the plan until close()
         self._handle = ctypes.c_void_p()
         self.n_obs, self.n_ens = n, N

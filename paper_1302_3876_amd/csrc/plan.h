@@ -10,6 +10,16 @@ namespace enkf {
 size_t dtype_size(enkf_dtype d);
 enkf_status validate_desc(const enkf_sm_desc* d);
 
+// Slots of Plan::norms (device, FP64).
+enum NormSlot : int {
+  kNrmRho = 0,    // ||rho||_F^2 of the last residual
+  kNrmD = 1,      // ||D||_F^2 of the solve
+  kNrmScale = 2,  // ||R^{-1} x||_F^2 of the right-hand side narrowed next (FP16 forms)
+  kNrmZ = 3,      // ||Z||_F^2 (diagnostics)
+  kNrmW = 4,      // estimate of ||W||_2 (diagnostics, per factorisation)
+  kNrmPart = 8    // reduction partials
+};
+
 struct Plan {
   enkf_sm_desc desc{};
   int max_nrhs = 0;
@@ -33,17 +43,18 @@ struct Plan {
   // blocked
   int block = 0;                // panel width b
   int npanel = 0;
-  double* Minv = nullptr;       // npanel x (b x b) inverse panel matrices
+  double* Sfac = nullptr;       // npanel x (b x b) S = D^{-1/2} L^{-1} of M = L D L^T
   double* Pbuf = nullptr;       // b x (N + max_nrhs) panel products
   double* Qbuf = nullptr;       // b x max(N, max_nrhs)
   // mixed precision (math narrower than dtype): FP32 working copies
   bool mixed = false;
   bool refine64 = false;        // FP64 blocked solve with FP64 refinement
+  bool diagnose = false;        // ENKF_FLAG_DIAGNOSE on an FP64, diagonal-R plan
   enkf_dtype wdt = ENKF_F64;    // working storage type of U, panels, Z-sweeps
   void* Vw = nullptr;           // FP32 copy of V (mixed)
   void* Zw = nullptr;           // FP32 correction (mixed), n x max_nrhs
   double* rho = nullptr;        // FP64 residual (mixed), n x max_nrhs
-  double* norms = nullptr;      // [0] ||rho||^2, [1] ||D||^2 (mixed)
+  double* norms = nullptr;      // slots kNrm* below, then reduction partials
   double* res_part = nullptr;   // per-block sums of rho^2 of the residual product
   int64_t res_part_cap = 0;
   // pivoting (plain)
@@ -69,6 +80,10 @@ struct Plan {
 
   enkf_status create(const enkf_sm_desc& d, const double* r, const void* V, int64_t ldv, hipStream_t s);
   enkf_status factor();
+  // ENKF_FLAG_DIAGNOSE: ||W||_2 estimate after a factorisation; after a
+  // synchronous solve, the residual (if the form has none), ||Z|| and eta.
+  enkf_status diag_factor();
+  enkf_status diag_solve(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz);
   enkf_status solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, enkf_sm_info* info);
   // factor() and solve() together (plain: one launch per level for U and Z)
   enkf_status factor_solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, enkf_sm_info* info);

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <limits>
 
+#include "diag.h"
 #include "gemm_lowp.h"
 #include "gemm_mfma.h"
 #include "panel.h"
@@ -75,6 +76,9 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   // backward stable, a few residual corrections restore the level formula's
   // accuracy on ill-conditioned systems
   refine64 = blocked && d.dtype == ENKF_F64 && d.math == ENKF_MATH_F64 && d.refine_max_iter > 0;
+  // diagnostics need an FP64 V for the residual and a diagonal R (diag_factor
+  // and diag_solve skip a plan with a block-diagonal R)
+  diagnose = (d.flags & ENKF_FLAG_DIAGNOSE) != 0 && d.dtype == ENKF_F64 && N <= wnorm_max_n_ens();
   wdt = mixed ? ENKF_F32 : d.dtype;
   const size_t wes = dtype_size(wdt);
   if (blocked) {
@@ -103,12 +107,12 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
       for (int m = 1; m <= max_nrhs; ++m) tnp = std::max(tnp, tn_partial_elems(n, bl, m));
     }
   }
-  if (mixed || refine64)
+  if (mixed || refine64 || diagnose)
     for (int m = 1; m <= max_nrhs; ++m) tnp = std::max(tnp, tn_partial_elems(n, N, m));
   const size_t oTn = take(sizeof(double) * (size_t)tnp);
   // right factor of an nn product, converted: inner dimension <= N, columns <= mcols
   const size_t oBt = take(nn_bt_bytes(N, mcols));
-  size_t oP0 = 0, oP1 = 0, oMinv = 0, oPbuf = 0, oQbuf = 0, oVw = 0, oZw = 0, oRho = 0, oNorm = 0, oResPart = 0;
+  size_t oP0 = 0, oP1 = 0, oSfac = 0, oPbuf = 0, oQbuf = 0, oVw = 0, oZw = 0, oRho = 0, oNorm = 0, oResPart = 0;
   size_t oGc = 0, oCb = 0, oPerm = 0, oRem = 0, oAct = 0;
   if (!blocked) {
     const size_t part_elems = (size_t)level_row_blocks(d.dtype, 1, n) * (N + max_nrhs);
@@ -122,7 +126,7 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
       oAct = take(sizeof(int32_t) * 2 * (size_t)(N + max_nrhs));
     }
   } else {
-    oMinv = take(sizeof(double) * (size_t)npanel * block * block);
+    oSfac = take(sizeof(double) * (size_t)npanel * block * block);
     oPbuf = take(sizeof(double) * (size_t)block * (N + mcols));
     oQbuf = take(sizeof(double) * (size_t)block * mcols);
   }
@@ -130,9 +134,9 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
     oVw = take((size_t)ldu * N * sizeof(float));
     oZw = take((size_t)ldu * mcols * sizeof(float));
   }
-  if (mixed || refine64) {
+  if (mixed || refine64 || diagnose) {
     oRho = take((size_t)ldu * mcols * sizeof(double));
-    oNorm = take(sizeof(double) * (2 + (size_t)norm_partial_elems()));
+    oNorm = take(sizeof(double) * (kNrmPart + (size_t)std::max(norm_partial_elems(), wnorm_partial_elems())));
     res_part_cap = nn_residual_part_elems(n, mcols);
     oResPart = take(sizeof(double) * (size_t)res_part_cap);
   }
@@ -161,7 +165,7 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
       act[1] = act[0] + N + max_nrhs;
     }
   } else {
-    Minv = reinterpret_cast<double*>(ws + oMinv);
+    Sfac = reinterpret_cast<double*>(ws + oSfac);
     Pbuf = reinterpret_cast<double*>(ws + oPbuf);
     Qbuf = reinterpret_cast<double*>(ws + oQbuf);
   }
@@ -169,13 +173,14 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
     Vw = ws + oVw;
     Zw = ws + oZw;
   }
-  if (mixed || refine64) {
+  if (mixed || refine64 || diagnose) {
     rho = reinterpret_cast<double*>(ws + oRho);
     norms = reinterpret_cast<double*>(ws + oNorm);
     res_part = reinterpret_cast<double*>(ws + oResPart);
   }
   ENKF_HIP_CHECK(hipMemsetAsync(ws + oStat, 0, sizeof(unsigned) * 4, stream));
   last.rel_residual = -1.0;
+  last.backward_error = -1.0;
   return ENKF_SUCCESS;
 }
 
@@ -223,7 +228,48 @@ enkf_status Plan::block_step1(enkf_dtype dt, int m, const void* X, int64_t ldx, 
   return launch_block_solve(dt, max_bs, nblk, m, boff, bpoff, Lf, X, ldx, Y, ldy, stream);
 }
 
-enkf_status Plan::factor() { return desc.algo == ENKF_SM_PLAIN ? factor_plain() : factor_blocked(); }
+enkf_status Plan::factor() {
+  enkf_status st = desc.algo == ENKF_SM_PLAIN ? factor_plain() : factor_blocked();
+  if (st != ENKF_SUCCESS) return st;
+  return diag_factor();
+}
+
+// ------------------------------------------------------------------ diagnostics
+enkf_status Plan::diag_factor() {
+  if (!diagnose || block_r) return ENKF_SUCCESS;
+  const int64_t n = desc.n_obs;
+  const int N = desc.n_ens;
+  enkf_status st = launch_tn(ENKF_F64, n, N, N, V, ldv, V, ldv, G, N, tn_part, stream);
+  if (st != ENKF_SUCCESS) return st;
+  return launch_wnorm_estimate(n, N, r, G, N, norms + kNrmPart, norms + kNrmW, stream);
+}
+
+// After a synchronous solve: the FP64 residual of Z unless the form left
+// it (plain and unrefined blocked solves; not possible when Z overwrote D),
+// ||Z||^2, and eta = ||rho|| / (||W||_2 ||Z|| + ||D||) into `last`.
+enkf_status Plan::diag_solve(int nrhs, const void* D, int64_t ldd, const void* Z, int64_t ldz) {
+  last.backward_error = -1.0;
+  if (!diagnose || block_r || nrhs == 0) return ENKF_SUCCESS;
+  enkf_status st;
+  if (!(mixed || refine64)) {
+    const uintptr_t d0 = (uintptr_t)D, d1 = d0 + ((size_t)ldd * (nrhs - 1) + desc.n_obs) * es;
+    const uintptr_t z0 = (uintptr_t)Z, z1 = z0 + ((size_t)ldz * (nrhs - 1) + desc.n_obs) * es;
+    if (z0 < d1 && d0 < z1) return ENKF_SUCCESS;
+    st = residual64(nrhs, D, ldd, Z, ldz, true);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  st = launch_sumsq(desc.n_obs, nrhs, static_cast<const double*>(Z), ldz, nullptr, norms + kNrmPart, norms + kNrmZ,
+                    stream);
+  if (st != ENKF_SUCCESS) return st;
+  double h[kNrmW + 1];
+  ENKF_HIP_CHECK(hipMemcpyAsync(h, norms, sizeof(h), hipMemcpyDeviceToHost, stream));
+  ENKF_HIP_CHECK(hipStreamSynchronize(stream));
+  const double rn = std::sqrt(h[kNrmRho]), dn = std::sqrt(h[kNrmD]), zn = std::sqrt(h[kNrmZ]);
+  last.rel_residual = dn > 0.0 ? rn / dn : rn;
+  const double den = h[kNrmW] * zn + dn;
+  last.backward_error = den > 0.0 ? rn / den : rn;
+  return ENKF_SUCCESS;
+}
 
 // ------------------------------------------------------------------ plain
 enkf_status Plan::factor_plain() {
@@ -544,7 +590,11 @@ enkf_status Plan::factor_solve(int nrhs, const void* D, int64_t ldd, void* Z, in
   last.refine_iters = 0;
   last.rel_residual = -1.0;
   if (st != ENKF_SUCCESS) return st;
-  return info ? get_info(info) : ENKF_SUCCESS;
+  st = diag_factor();
+  if (st != ENKF_SUCCESS) return st;
+  if (!info) return ENKF_SUCCESS;
+  st = diag_solve(nrhs, D, ldd, Z, ldz);
+  return st != ENKF_SUCCESS ? st : get_info(info);
 }
 
 // ------------------------------------------------------------------ blocked
@@ -586,9 +636,9 @@ enkf_status Plan::factor_blocked() {
     }
     {
       TimedLaunch tl(&timing, stream, KC_PANEL_FACTOR, 0.0, (double)bl * bl * bl + 2.0 * bl * bl * mrest);
-      st = launch_panel_factor(bl, Pbuf, bl, gamma + k0, Minv + (size_t)p * block * block, status, stream);
+      st = launch_panel_factor(bl, Pbuf, bl, gamma + k0, Sfac + (size_t)p * block * block, status, stream);
       if (st != ENKF_SUCCESS) return st;
-      st = launch_small_gemm(bl, mrest, Minv + (size_t)p * block * block, Pbuf + (size_t)bl * bl, bl, Qbuf, stream);
+      st = launch_panel_apply(bl, mrest, Sfac + (size_t)p * block * block, Pbuf + (size_t)bl * bl, bl, Qbuf, stream);
       if (st != ENKF_SUCCESS) return st;
     }
     if (mrest > 0) {
@@ -640,7 +690,7 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
     }
     {
       TimedLaunch tl(&timing, stream, KC_PANEL_FACTOR, 0.0, 2.0 * bl * bl * nrhs);
-      st = launch_small_gemm(bl, nrhs, Minv + (size_t)p * block * block, Pbuf, bl, Qbuf, stream);
+      st = launch_panel_apply(bl, nrhs, Sfac + (size_t)p * block * block, Pbuf, bl, Qbuf, stream);
       if (st != ENKF_SUCCESS) return st;
     }
     NnArgs a{};
@@ -668,21 +718,29 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
 // with rho = D - (R Z + V (V^T Z)) formed in FP64. The narrowing copy of D
 // or rho also applies R^{-1} (Step 1), so the panels start from it. Inputs
 // with the FP32 exponent range (FP32, BF16 parts) take R^{-1} rho straight
-// from the residual product; the FP16 forms divide rho by its rms first (a
-// shrinking residual would leave the FP16 range), so they keep the copy.
+// from the residual product. The FP16 forms divide every right-hand side by
+// the rms of R^{-1} times it (norms[2]) before narrowing and multiply the
+// correction back, so neither a large R^{-1} D nor a shrinking residual
+// leaves the FP16 range; they keep the FP64 copy of rho for that.
 enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync) {
   const int64_t n = desc.n_obs;
   last.refine_iters = 0;
   last.rel_residual = -1.0;
   if (nrhs == 0) return ENKF_SUCCESS;
   float* W = static_cast<float*>(Zw);
-  enkf_status st = launch_convert(n, nrhs, static_cast<const double*>(D), ldd, W, ldu, nullptr, r, status, stream);
+  const bool fp16 = desc.math == ENKF_MATH_F16 || desc.math == ENKF_MATH_F16X2;
+  double* scale = fp16 ? norms + kNrmScale : nullptr;
+  enkf_status st;
+  if (fp16) {
+    st = launch_sumsq(n, nrhs, static_cast<const double*>(D), ldd, r, norms + kNrmPart, scale, stream);
+    if (st != ENKF_SUCCESS) return st;
+  }
+  st = launch_convert(n, nrhs, static_cast<const double*>(D), ldd, W, ldu, scale, r, status, stream);
   if (st != ENKF_SUCCESS) return st;
   st = solve_blocked(nrhs, W, ldu, W, ldu, true);
   if (st != ENKF_SUCCESS) return st;
-  st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, false, nullptr, stream);
+  st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, false, scale, stream);
   if (st != ENKF_SUCCESS) return st;
-  const bool fp16 = desc.math == ENKF_MATH_F16 || desc.math == ENKF_MATH_F16X2;
   const int maxit = desc.refine_max_iter;
   for (int it = 0; it <= maxit; ++it) {
     if (!sync && it == maxit) break;
@@ -696,12 +754,14 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
       if (last.rel_residual <= desc.refine_tol || it == maxit) break;
     }
     if (fp16) {
-      st = launch_convert(n, nrhs, rho, ldu, W, ldu, norms, r, status, stream);
+      st = launch_sumsq(n, nrhs, rho, ldu, r, norms + kNrmPart, scale, stream);
+      if (st != ENKF_SUCCESS) return st;
+      st = launch_convert(n, nrhs, rho, ldu, W, ldu, scale, r, status, stream);
       if (st != ENKF_SUCCESS) return st;
     }
     st = solve_blocked(nrhs, W, ldu, W, ldu, true);
     if (st != ENKF_SUCCESS) return st;
-    st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, true, fp16 ? norms : nullptr, stream);
+    st = launch_widen(n, nrhs, W, ldu, static_cast<double*>(Z), ldz, true, scale, stream);
     if (st != ENKF_SUCCESS) return st;
     last.refine_iters = it + 1;
   }
@@ -779,7 +839,7 @@ enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z
   }
   // ||D||^2, constant over the solve
   if (!d_norm) return ENKF_SUCCESS;
-  return launch_sumsq(n, nrhs, static_cast<const double*>(D), ldd, norms + 2, norms + 1, stream);
+  return launch_sumsq(n, nrhs, static_cast<const double*>(D), ldd, nullptr, norms + kNrmPart, norms + kNrmD, stream);
 }
 
 // ------------------------------------------------------------------ common
@@ -814,6 +874,8 @@ enkf_status Plan::solve(int nrhs, const void* D, int64_t ldd, void* Z, int64_t l
   }
   if (st != ENKF_SUCCESS) return st;
   if (info) {
+    st = diag_solve(nrhs, D, ldd, Z, ldz);
+    if (st != ENKF_SUCCESS) return st;
     st = get_info(info);
     if (st != ENKF_SUCCESS) return st;
     if ((mixed || refine64) && desc.refine_tol > 0.0 && nrhs > 0 && !(last.rel_residual <= desc.refine_tol))
@@ -866,6 +928,7 @@ enkf_status Plan::get_info(enkf_sm_info* info) {
   out.gamma_min = *std::min_element(g.begin(), g.end());
   out.gamma_max = *std::max_element(g.begin(), g.end());
   out.device_status = (int32_t)st;
+  out.hip_error = (int32_t)hipPeekAtLastError();
   *info = out;
   if (st != 0)
     return fail(static_cast<enkf_status>(st), "a kernel latched an error (r_i or gamma_k not finite or not > 0)");

@@ -97,7 +97,7 @@ enkf_status validate_desc(const enkf_sm_desc* d) {
   if (d->dtype != ENKF_F64 && d->dtype != ENKF_F32) return fail(ENKF_ERR_INVALID_ARG, "unknown dtype");
   if (d->algo != ENKF_SM_PLAIN && d->algo != ENKF_SM_BLOCKED) return fail(ENKF_ERR_INVALID_ARG, "unknown algo");
   if (d->math < ENKF_MATH_F64 || d->math > ENKF_MATH_F16X2) return fail(ENKF_ERR_INVALID_ARG, "unknown math");
-  if (d->flags & ~ENKF_FLAG_PIVOT) return fail(ENKF_ERR_INVALID_ARG, "unknown flag bits");
+  if (d->flags & ~(ENKF_FLAG_PIVOT | ENKF_FLAG_DIAGNOSE)) return fail(ENKF_ERR_INVALID_ARG, "unknown flag bits");
   if (d->max_nrhs < 0) return fail(ENKF_ERR_INVALID_ARG, "max_nrhs must be >= 0");
   if (d->refine_max_iter < 0) return fail(ENKF_ERR_INVALID_ARG, "refine_max_iter must be >= 0");
   if (!(d->refine_tol >= 0.0)) return fail(ENKF_ERR_INVALID_ARG, "refine_tol must be >= 0");
@@ -223,6 +223,23 @@ enkf_status enkf_sm_refactor(enkf_sm_plan plan, const double* r, const void* V, 
   return p->factor();
 }
 
+// D and Z of a solve: the plain and the unrefined blocked solves run in
+// place (Z == D with the same leading dimension); the refined and mixed
+// solves read D again for every residual, so they need it untouched and take
+// no overlap at all. Any other overlap of the two column ranges is refused.
+static enkf_status check_rhs_overlap(const Plan* p, const char* where, int32_t nrhs, const void* D, int64_t ldd,
+                                     const void* Z, int64_t ldz) {
+  const size_t es = dtype_size(p->desc.dtype);
+  const uintptr_t d0 = (uintptr_t)D, d1 = d0 + ((size_t)ldd * (nrhs - 1) + p->desc.n_obs) * es;
+  const uintptr_t z0 = (uintptr_t)Z, z1 = z0 + ((size_t)ldz * (nrhs - 1) + p->desc.n_obs) * es;
+  if (!(z0 < d1 && d0 < z1)) return ENKF_SUCCESS;
+  if (p->mixed || p->refine64)
+    return fail(ENKF_ERR_INVALID_ARG, std::string(where) + ": Z overlaps D, and a refined solve reads D after writing Z");
+  if (D != Z || ldd != ldz)
+    return fail(ENKF_ERR_INVALID_ARG, std::string(where) + ": Z overlaps D other than in place with the same leading dimension");
+  return ENKF_SUCCESS;
+}
+
 enkf_status enkf_sm_solve(enkf_sm_plan plan, int32_t nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz,
                           enkf_sm_info* info) {
   if (!plan) return fail(ENKF_ERR_INVALID_ARG, "solve: plan is NULL");
@@ -231,7 +248,8 @@ enkf_status enkf_sm_solve(enkf_sm_plan plan, int32_t nrhs, const void* D, int64_
   if (nrhs > 0) {
     if (!D || !Z) return fail(ENKF_ERR_INVALID_ARG, "solve: D or Z is NULL");
     if (ldd < p->desc.n_obs || ldz < p->desc.n_obs) return fail(ENKF_ERR_INVALID_ARG, "solve: leading dimension < n_obs");
-    if (D == Z && ldd != ldz) return fail(ENKF_ERR_INVALID_ARG, "solve: Z aliases D with a different leading dimension");
+    enkf_status st = check_rhs_overlap(p, "solve", nrhs, D, ldd, Z, ldz);
+    if (st != ENKF_SUCCESS) return st;
   }
   return p->solve(nrhs, D, ldd, Z, ldz, info);
 }
@@ -248,7 +266,8 @@ enkf_status enkf_sm_factor_solve(enkf_sm_plan plan, const double* r, const void*
     if (!D || !Z) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: D or Z is NULL");
     if (ldd < p->desc.n_obs || ldz < p->desc.n_obs)
       return fail(ENKF_ERR_INVALID_ARG, "factor_solve: leading dimension < n_obs");
-    if (D == Z && ldd != ldz) return fail(ENKF_ERR_INVALID_ARG, "factor_solve: Z aliases D with a different leading dimension");
+    enkf_status st = check_rhs_overlap(p, "factor_solve", nrhs, D, ldd, Z, ldz);
+    if (st != ENKF_SUCCESS) return st;
   }
   p->r = r;
   p->V = V;

@@ -104,10 +104,14 @@ def test_mixed_every_math_well_conditioned(math):
     fp64_gate(r, V, D, host(Z), oracle.sm_solve(r, V, D)["Z"])
 
 
-# f16x2 (~22 significant bits) contracts like FP32; bf16x3 (~16 bits) about
-# 0.3 per step on this data, so it needs more steps
 @pytest.mark.parametrize("math,maxit", [("bf16x3", 30), ("f16x2", 8), ("f32", 8)])
 def test_mixed_split_forms_reach_gate_on_c3_like_data(math, maxit):
+    """The split forms on c3-distributed data refine to the mixed gate,
+    judged by the host's FP64 residual of the returned Z (the host's own
+    evaluation error is ~2e-12 of ||D|| on this data, measured against an
+    80-bit evaluation). The device's report is printed, not gated: the
+    refinement drives the device's own FP64 residual to its stopping
+    tolerance, so that report sits at or below the true residual."""
     import torch
     n, N, b = 131072, 64, 32
     w = synth.direct_vd_workload("c3-small", n, N, seed=6000)
@@ -115,7 +119,9 @@ def test_mixed_split_forms_reach_gate_on_c3_like_data(math, maxit):
                       refine_tol=1e-10)
     Z, info = plan.solve(dev(w.D), info=True)
     torch.cuda.synchronize()
-    print(math, info, flush=True)
+    rr = oracle.rel_residual(w.r, w.V, host(Z), w.D)
+    print(math, info, "host relres", rr, flush=True)
+    assert rr <= 1e-10
     assert info["rel_residual"] <= 1e-10
 
 
@@ -163,11 +169,12 @@ def test_analysis_ex_fp32_ensemble(math, tol):
 
 
 def test_blocked_fp64_refinement_restores_accuracy():
-    """FP64 panels with FP64 refinement (F64/F64 and refine_max_iter > 0):
-    on an ill-conditioned system (R = 1e-4 I, large ensemble spread, the
-    capacitance matrix has condition ~1e5) the Woodbury panel update alone
-    leaves a residual far above the level formula's; one or two residual
-    corrections bring it to the oracle's level."""
+    """FP64 panels with FP64 refinement (F64/F64 and refine_max_iter > 0) on
+    an ill-conditioned system (R = 1e-4 I, large ensemble spread, the
+    capacitance matrix has condition ~1e5). The panel update applies M^{-1}
+    through its LDL^T factor (two triangular products), so the unrefined
+    solve already reaches the oracle's residual level; two residual
+    corrections keep it there."""
     import torch
     import paper_1302_3876_amd as pk
     n, N = 20000, 96
@@ -186,9 +193,10 @@ def test_blocked_fp64_refinement_restores_accuracy():
     torch.cuda.synchronize()
     rr0 = oracle.rel_residual(r, V, Z0, D)
     rr = oracle.rel_residual(r, V, host(Z), D)
+    print({"unrefined": rr0, "refined": rr, "oracle": rr_or}, flush=True)
     assert info["refine_iters"] == 2
     assert rr <= max(1e-12, 2.0 * rr_or), (rr, rr_or, rr0)
-    assert rr < rr0
+    assert rr0 <= max(1e-12, 2.0 * rr_or), (rr, rr_or, rr0)
 
 
 def test_mixed_solve_latches_bad_r():
@@ -208,3 +216,119 @@ def test_mixed_solve_latches_bad_r():
         plan.solve(dev(D), info=True)
     assert e.value.code == 2
     plan.close()
+
+
+@pytest.mark.parametrize("math,refine", [("f32", 2), ("f64", 1), ("bf16x3", 3)])
+def test_refined_solves_reject_overlapping_rhs(math, refine):
+    """Refined and mixed solves read D again for every residual after Z has
+    been written, so any overlap of Z with D is refused on the host (in place,
+    or shifted by a column); the out-of-place solve still matches the oracle."""
+    import torch
+    pk = _pk()
+    n, N = 2000, 16
+    r, V, D = synth.small_vd(n, N, seed=80)
+    rd, Vd = dev(r), dev(V)
+    plan = pk.Plan(rd, Vd, algo="blocked", math=math, block=8, refine_max_iter=refine, refine_tol=0.0)
+    Dd = dev(D)
+    for call in (lambda: plan.solve(Dd, Dd), lambda: plan.factor_solve(rd, Vd, Dd, Dd)):
+        with pytest.raises(pk.EnkfError) as e:
+            call()
+        assert e.value.code == 1
+    big = pk.colmajor(n, N + 1)
+    big[:, :N].copy_(torch.as_tensor(D))
+    with pytest.raises(pk.EnkfError) as e:
+        plan.solve(big[:, :N], big[:, 1:])
+    assert e.value.code == 1
+    Z, info = plan.solve(Dd, info=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(Dd), D)
+    fp64_gate(r, V, D, host(Z), oracle.sm_solve(r, V, D)["Z"])
+
+
+def test_unrefined_solves_reject_partial_overlap():
+    """The plain and the unrefined blocked solves run in place (Z == D), but
+    a Z that overlaps D otherwise is refused."""
+    import torch
+    pk = _pk()
+    n, N = 1500, 12
+    r, V, D = synth.small_vd(n, N, seed=82)
+    for algo in ("plain", "blocked"):
+        plan = pk.Plan(dev(r), dev(V), algo=algo, block=4 if algo == "blocked" else 0)
+        big = pk.colmajor(n, N + 1)
+        big[:, :N].copy_(torch.as_tensor(D))
+        with pytest.raises(pk.EnkfError) as e:
+            plan.solve(big[:, :N], big[:, 1:])
+        assert e.value.code == 1
+        Dd = dev(D)
+        Z = plan.solve(Dd, Dd)
+        torch.cuda.synchronize()
+        fp64_gate(r, V, D, host(Z), oracle.sm_solve(r, V, D)["Z"])
+
+
+@pytest.mark.parametrize("math", ["f16", "f16x2"])
+def test_fp16_forms_scale_large_right_hand_sides(math):
+    """The well-conditioned system of test_mixed_every_math_well_conditioned
+    with R and V V^T both scaled by 1e-6 (the same pivots): R^{-1} D is then
+    ~1e6, beyond the FP16 range (65504). The FP16 forms divide each
+    right-hand side by the rms of R^{-1} times it before narrowing, so the
+    solve converges to the same accuracy instead of overflowing."""
+    import torch
+    n, N = 1000, 16
+    r, V, D = synth.small_vd(n, N, seed=77, r_range=(0.5, 2.0), v_scale=0.5)
+    r, V = r * 1e-6, V * 1e-3
+    plan = _pk().Plan(dev(r), dev(V), algo="blocked", math=math, block=16, refine_max_iter=12, refine_tol=1e-12)
+    Z, info = plan.solve(dev(D), info=True)
+    torch.cuda.synchronize()
+    Zh = host(Z)
+    print(math, info, flush=True)
+    assert np.all(np.isfinite(Zh))
+    assert oracle.rel_residual(r, V, Zh, D) <= 1e-12
+    fp64_gate(r, V, D, Zh, oracle.sm_solve(r, V, D)["Z"])
+
+
+@pytest.mark.parametrize("algo,math,refine", [("plain", "f64", 0), ("blocked", "f64", 0), ("blocked", "f64", 1),
+                                              ("blocked", "f32", 4), ("blocked", "f32", 0)])
+def test_diagnose_flag_reports_backward_error(algo, math, refine):
+    """ENKF_FLAG_DIAGNOSE: every synchronous solve reports the relative
+    residual and eta = ||D - W Z|| / (||W||_2 ||Z|| + ||D||) of its Z.
+    (1) The device's ||W||_2 estimate (max r + the Rayleigh quotient of V^T V
+    after 60 power steps), recovered from the two reports, against the
+    oracle's (max r + the largest eigenvalue of the Gram): within 2%.
+    (2) Where the residual is far above the rounding of its evaluation (the
+    unrefined FP32-panel solve, ~1e-6) the reports match the host's FP64
+    values of the returned Z to 1e-6. (3) Where it is at the rounding floor
+    (FP64 forms, ~1e-13) both evaluations are mostly rounding: the device
+    report stays below twice the host's plus 1e-13. An in-place solve and a
+    plan without the flag report -1."""
+    import torch
+    pk = _pk()
+    w = synth.c2(n_state=65536, n_ens=48)
+    Vo, Do = oracle.build_vd(w.XB, w.obs_idx, w.y, w.E)
+    plan = pk.Plan(dev(w.r), dev(Vo), algo=algo, math=math, block=16 if algo == "blocked" else 0,
+                   refine_max_iter=refine, refine_tol=0.0, diagnose=True)
+    Z, info = plan.solve(dev(Do), info=True)
+    torch.cuda.synchronize()
+    Zh = host(Z)
+    rr = oracle.rel_residual(w.r, Vo, Zh, Do)
+    eta = oracle.backward_error(w.r, Vo, Zh, Do)
+    dn, zn = np.linalg.norm(Do), np.linalg.norm(Zh)
+    w_dev = (info["rel_residual"] * dn / info["backward_error"] - dn) / zn
+    w_or = oracle.norm_w_estimate(w.r, Vo)
+    print(algo, math, refine, info, {"relres": rr, "eta": eta, "w_dev": w_dev, "w_oracle": w_or}, flush=True)
+    assert info["backward_error"] > 0 and info["rel_residual"] > 0 and info["hip_error"] == 0
+    assert abs(w_dev - w_or) <= 0.02 * w_or
+    if math == "f32" and refine == 0:
+        assert rr > 1e-8
+        assert abs(info["rel_residual"] - rr) <= 1e-6 * rr
+        assert abs(info["backward_error"] - eta) <= 0.02 * eta
+    else:
+        assert info["rel_residual"] <= 2.0 * rr + 1e-13
+        assert info["backward_error"] <= 1e-15
+    if algo == "plain":
+        Dd = dev(Do)
+        _, info2 = plan.solve(Dd, Dd, info=True)
+        assert info2["backward_error"] == -1.0
+    plan.close()
+    plain = pk.Plan(dev(w.r), dev(Vo))
+    _, info3 = plain.solve(dev(Do), info=True)
+    assert info3["backward_error"] == -1.0 and info3["rel_residual"] == -1.0

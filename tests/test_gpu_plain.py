@@ -181,11 +181,27 @@ def test_c2_full_path_fp64_full_size():
     Zo = oracle.sm_solve(w.r, Vo, Do)["Z"]
     g = fp64_gate(w.r, Vo, Do, Z, Zo)
     print(g, flush=True)
+    # the blocked form on the same inputs (one panel of 96 levels), without
+    # refinement: the panel applies M^{-1} through its LDL^T factor
+    import torch
+    pk = _pk()
+    bplan = pk.Plan(dev(w.r), dev(Vo), algo="blocked")
+    Zb = host(bplan.solve(dev(Do)))
+    torch.cuda.synchronize()
+    gb = fp64_gate(w.r, Vo, Do, Zb, Zo)
+    print({"blocked": gb}, flush=True)
+    # every element of the increment, not only the norm. Here the oracle's
+    # own rounding dominates: its ascending FP64 sums over 262,144
+    # observations leave a relative residual of 7e-11 (the device's is
+    # ~7e-13), and on the host its increment differs from that of an
+    # LDL^T-blocked solve (relative residual 4e-12) by 1.5e-10 of the largest
+    # increment; bound: ten times the larger of the two relative residuals
     XAo = oracle.analysis(w.XB, Vo, Zo)
-    assert rel(XA - w.XB, XAo - w.XB) < 1e-8
-    # every element of the increment, not only the norm
     inc, inco = XA - w.XB, XAo - w.XB
-    assert np.max(np.abs(inc - inco)) <= 1e-8 * np.max(np.abs(inco))
+    einc = np.max(np.abs(inc - inco)) / np.max(np.abs(inco))
+    bound = 10.0 * max(g["relres_gpu"], g["relres_oracle"])
+    print({"increment_max_rel": einc, "bound": bound}, flush=True)
+    assert einc <= bound
 
 
 @pytest.mark.slow
@@ -201,5 +217,9 @@ def test_c2_full_path_fp32_full_size():
     rz = rel(Z, Zo)
     XAo = oracle.analysis(XB32, Vo, Zo)
     ra = rel(XA - XB32, XAo - XB32)
-    print({"z_rel": rz, "increment_rel": ra}, flush=True)
-    assert rz < 1e-2 and ra < 1e-2
+    # FP32 storage and arithmetic: forward error up to kappa(W) times the
+    # FP32 rounding unit (2^-24)
+    kappa = oracle.norm_w_estimate(w.r, Vo) / float(np.min(w.r))
+    bound = kappa * 2.0 ** -24
+    print({"z_rel": rz, "increment_rel": ra, "kappa": kappa, "bound": bound}, flush=True)
+    assert rz < bound and ra < bound
