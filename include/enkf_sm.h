@@ -93,6 +93,15 @@ typedef enum {
  * residual D - (R Z + V (V^T Z)) for it; an in-place solve (Z overwrote D)
  * reports -1. */
 #define ENKF_FLAG_DIAGNOSE 0x2u
+/* Panel width by measurement (BLOCKED with block = 0): enkf_sm_init times
+ * the factorisation and one solve of min(N, max_nrhs) right-hand sides (the
+ * columns of V; no refinement) on the plan's own data for b = 32, 64, 96,
+ * 128 (those <= N) and keeps the fastest (eq. SWM with a rank-b term: the
+ * panel products grow with b, the passes over the trailing columns shrink
+ * as 1/b). A shape (n_obs, n_ens, dtype, math, max_nrhs) tuned before in
+ * the process reuses its width. Without the flag, block = 0 is min(N, 128).
+ * The timing allocates a scratch right-hand side for the duration of init. */
+#define ENKF_FLAG_AUTOTUNE 0x4u
 
 typedef struct {
     int64_t n_obs;          /* n >= 1 */
@@ -118,6 +127,7 @@ typedef struct {
     double gamma_max;
     int32_t device_status;  /* enkf_status latched by kernels (0 = none) */
     int32_t hip_error;      /* hipPeekAtLastError() of the calling thread when the info was taken (0 = none) */
+    int32_t block;          /* panel width in use (BLOCKED; 1 for PLAIN) */
 } enkf_sm_info;
 
 typedef struct enkf_sm_plan_s* enkf_sm_plan;
@@ -269,6 +279,11 @@ enkf_status enkf_analysis_ex(enkf_sm_plan plan, int64_t n_state, enkf_dtype x_dt
  * solve's refinement record and any latched device error. */
 enkf_status enkf_sm_get_info(enkf_sm_plan plan, enkf_sm_info* info);
 
+/* What ENKF_FLAG_AUTOTUNE measured at init: *count (<= 4) widths and the
+ * milliseconds of one factorisation + solve with each (HOST arrays of 4, or
+ * NULL). *count = 0 when the plan did not tune (or reused a tuned width). */
+enkf_status enkf_sm_get_tuning(enkf_sm_plan plan, int32_t* widths, double* ms, int32_t* count);
+
 /* Copy the pivots gamma_1..gamma_N (FP64, HOST buffer of n_ens entries) and,
  * when pivoting, the level order (HOST int32 buffer or NULL: entry k is the V
  * column used at level k). Synchronises. */
@@ -285,7 +300,9 @@ enkf_status enkf_sm_get_pivots(enkf_sm_plan plan, double* gamma_host, int32_t* p
  * 2 build, 3 analysis update, 4 split-K products, 5 panel updates (blocked),
  * 6 panel factorisations (blocked), 7 FP64 residuals (refinement),
  * 8 Step 1 (with the plain form's first look-ahead products), 9 level sweeps
- * of a fused factorisation + solve (plain), 10 localized analysis updates.
+ * of a fused factorisation + solve (plain), 10 localized analysis updates,
+ * 11 the products G = V^T Z of the FP64 residuals (class 7 is then the
+ * residual D - (R Z + V G) itself).
  */
 enkf_status enkf_sm_set_timing(enkf_sm_plan plan, int32_t enable);
 enkf_status enkf_sm_get_timing(enkf_sm_plan plan, int32_t kernel_class, double* total_ms, int64_t* launches,

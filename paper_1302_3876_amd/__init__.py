@@ -27,11 +27,12 @@ ENKF_SM_PLAIN, ENKF_SM_BLOCKED = 0, 1
 MATH = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16x3": 4, "f16x2": 5}
 ENKF_FLAG_PIVOT = 0x1
 ENKF_FLAG_DIAGNOSE = 0x2
+ENKF_FLAG_AUTOTUNE = 0x4
 STATUS = {0: "ENKF_SUCCESS", 1: "ENKF_ERR_INVALID_ARG", 2: "ENKF_ERR_NOT_SPD", 3: "ENKF_ERR_NO_CONVERGENCE",
           4: "ENKF_ERR_HIP", 5: "ENKF_ERR_OUT_OF_MEMORY", 6: "ENKF_ERR_NOT_SUPPORTED"}
 KERNEL_CLASSES = {"factor_sweep": 0, "solve_sweep": 1, "build": 2, "analysis": 3, "gram": 4,
                   "panel_update": 5, "panel_factor": 6, "residual": 7, "step1": 8,
-                  "fused_sweep": 9, "localize": 10}
+                  "fused_sweep": 9, "localize": 10, "residual_tn": 11}
 
 
 class EnkfError(RuntimeError):
@@ -55,7 +56,7 @@ class LocalDesc(ctypes.Structure):
 class SmInfo(ctypes.Structure):
     _fields_ = [("refine_iters", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("backward_error", ctypes.c_double), ("gamma_min", ctypes.c_double), ("gamma_max", ctypes.c_double),
-                ("device_status", ctypes.c_int32), ("hip_error", ctypes.c_int32)]
+                ("device_status", ctypes.c_int32), ("hip_error", ctypes.c_int32), ("block", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -87,6 +88,7 @@ def lib():
     L.enkf_localized_analysis.argtypes = [vp, i64, vp, i64, vp, i64, vp, ctypes.c_double, i64, i64, vp, i64]
     L.enkf_sm_get_info.argtypes = [vp, ctypes.POINTER(SmInfo)]
     L.enkf_sm_get_pivots.argtypes = [vp, vp, vp]
+    L.enkf_sm_get_tuning.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
     L.enkf_sm_set_timing.argtypes = [vp, i32]
     L.enkf_sm_get_timing.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                      ctypes.POINTER(dbl)]
@@ -107,7 +109,7 @@ def lib():
     L.enkf_last_error_message.restype = ctypes.c_char_p
     for name in ("enkf_sm_validate_desc", "enkf_build_vd", "enkf_sm_init", "enkf_sm_init_block_r", "enkf_sm_refactor",
                  "enkf_sm_refactor_block_r", "enkf_sm_factor_solve", "enkf_sm_solve", "enkf_analysis",
-                 "enkf_analysis_ex", "enkf_localized_analysis", "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_set_timing", "enkf_sm_get_timing",
+                 "enkf_analysis_ex", "enkf_localized_analysis", "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_get_tuning", "enkf_sm_set_timing", "enkf_sm_get_timing",
                  "enkf_local_init", "enkf_local_analysis", "enkf_local_sync"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -228,7 +230,7 @@ class Plan:
 
     def __init__(self, r, V, algo: str = "plain", math: Optional[str] = None, block: int = 0, max_nrhs: int = 0,
                  refine_max_iter: int = 0, refine_tol: float = 0.0, pivot: bool = False, block_r=None,
-                 diagnose: bool = False):
+                 diagnose: bool = False, autotune: bool = False):
         torch = _torch()
         self.dtype = _dtype_code(V)
         if math is None:
@@ -237,7 +239,8 @@ class Plan:
         n, N = V.shape
         self.desc = SmDesc(n, N, self.dtype, ENKF_SM_PLAIN if algo == "plain" else ENKF_SM_BLOCKED, MATH[math],
                            block, max_nrhs, refine_max_iter, refine_tol,
-                           (ENKF_FLAG_PIVOT if pivot else 0) | (ENKF_FLAG_DIAGNOSE if diagnose else 0))
+                           (ENKF_FLAG_PIVOT if pivot else 0) | (ENKF_FLAG_DIAGNOSE if diagnose else 0)
+                           | (ENKF_FLAG_AUTOTUNE if autotune else 0))
         self._r, self._V = r, V  # borrowed by the plan until close()
         self._handle = ctypes.c_void_p()
         self.n_obs, self.n_ens = n, N
@@ -344,6 +347,17 @@ class Plan:
         inf = SmInfo()
         _check(lib().enkf_sm_get_info(self._handle, ctypes.byref(inf)), "enkf_sm_get_info")
         return inf.as_dict()
+
+    def tuning(self):
+        """{panel width: ms of one factorisation + solve} measured by
+        ENKF_FLAG_AUTOTUNE at init (empty if the plan did not tune)."""
+        import numpy as np
+        wd = np.zeros(4, dtype=np.int32)
+        ms = np.zeros(4, dtype=np.float64)
+        cnt = ctypes.c_int32(0)
+        _check(lib().enkf_sm_get_tuning(self._handle, ctypes.c_void_p(wd.ctypes.data), ctypes.c_void_p(ms.ctypes.data),
+                                        ctypes.byref(cnt)), "enkf_sm_get_tuning")
+        return {int(wd[i]): float(ms[i]) for i in range(cnt.value)}
 
     def pivots(self):
         import numpy as np

@@ -26,11 +26,12 @@ enum KernelClass : int {
   KC_GRAM = 4,         // split-K products V^T X (analysis G, residual, panels)
   KC_PANEL_UPDATE = 5, // blocked: X -= U_K Q (+ look-ahead products)
   KC_PANEL_FACTOR = 6, // blocked: b x b LDL^T and solves
-  KC_RESIDUAL = 7,     // FP64 residual of the refinement
+  KC_RESIDUAL = 7,     // FP64 residual of the refinement: D - (r o Z + V G)
   KC_STEP1 = 8,        // Step 1 (R^{-1} V, R^{-1} D) and the plain form's first products
   KC_FUSED_SWEEP = 9,  // plain: U- and Z-updates of one level in one launch (factor + solve)
   KC_LOCALIZE = 10,    // partially localized analysis update
-  KC_COUNT = 11
+  KC_RESIDUAL_TN = 11, // FP64 residual of the refinement: the product G = V^T Z
+  KC_COUNT = 12
 };
 
 void set_error(const std::string& msg);

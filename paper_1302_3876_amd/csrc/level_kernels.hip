@@ -45,10 +45,15 @@ template <> struct VecT<float, 1> { typedef float type; };
 // inside or wholly outside the rows; callers pass a valid row index (rows
 // past n are redirected to row 0 and their values never stored), so loads
 // carry no branches and all of a block's loads are in flight together.
-template <typename T, int VW>
+// STREAM: non-temporal accesses, for columns that are read and written once
+// per level and whose level working set exceeds the last-level cache (they
+// would only evict the vectors every column group re-reads).
+template <typename T, int VW, bool STREAM = false>
 __device__ __forceinline__ void load_vec(const T* __restrict__ p, int64_t row, T (&v)[VW]) {
   typedef typename VecT<T, VW>::type vt;
-  const vt x = *reinterpret_cast<const vt*>(p + row);
+  vt x;
+  if constexpr (STREAM) x = __builtin_nontemporal_load(reinterpret_cast<const vt*>(p + row));
+  else x = *reinterpret_cast<const vt*>(p + row);
   if constexpr (VW == 1) {
     v[0] = x;
   } else {
@@ -57,7 +62,7 @@ __device__ __forceinline__ void load_vec(const T* __restrict__ p, int64_t row, T
   }
 }
 
-template <typename T, int VW>
+template <typename T, int VW, bool STREAM = false>
 __device__ __forceinline__ void store_vec(T* __restrict__ p, int64_t row, const T (&v)[VW]) {
   typedef typename VecT<T, VW>::type vt;
   vt x;
@@ -67,7 +72,8 @@ __device__ __forceinline__ void store_vec(T* __restrict__ p, int64_t row, const 
 #pragma unroll
     for (int e = 0; e < VW; ++e) x[e] = v[e];
   }
-  *reinterpret_cast<vt*>(p + row) = x;
+  if constexpr (STREAM) __builtin_nontemporal_store(x, reinterpret_cast<vt*>(p + row));
+  else *reinterpret_cast<vt*>(p + row) = x;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -109,7 +115,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // MULTI: the grid has fewer row blocks than tiles and a block walks its
 // consecutive tiles (a separate instance: one-tile launches keep their
 // register budget).
-template <typename T, int VW, bool STEP1, bool LOOKAHEAD, bool OWN_GAMMA, bool MULTI>
+template <typename T, int VW, bool STEP1, bool LOOKAHEAD, bool OWN_GAMMA, bool MULTI, bool STREAM>
 __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
   constexpr int COLS = LV_COLS, RPT = LV_RPT;
   constexpr int64_t RPB = (int64_t)LV_THREADS * VW * RPT;   // rows of one tile
@@ -156,7 +162,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
     for (int c = 0; c < COLS; ++c) {
       const T* __restrict__ col = src + (int64_t)phys(min(col0 + c, a.m - 1)) * lds;
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) load_vec<T, VW>(col, rowc[r], xv[c][r]);
+      for (int r = 0; r < RPT; ++r) load_vec<T, VW, STREAM>(col, rowc[r], xv[c][r]);
     }
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
@@ -241,7 +247,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
           xv[c][r][e] = (T)x;
           if constexpr (LOOKAHEAD) acc[c] += vn[r][e] * (double)xv[c][r][e];
         }
-        if (c < ncol && rows[r] < n) store_vec<T, VW>(Out + (int64_t)phys(col0 + c) * ldo, rows[r], xv[c][r]);
+        if (c < ncol && rows[r] < n) store_vec<T, VW, STREAM>(Out + (int64_t)phys(col0 + c) * ldo, rows[r], xv[c][r]);
       }
     }
   }
@@ -276,22 +282,26 @@ __global__ __launch_bounds__(kWave) void gamma_kernel(const double* __restrict__
   }
 }
 
-template <typename T, int VW, bool MULTI>
+template <typename T, int VW, bool MULTI, bool STREAM>
 enkf_status launch_flags(const LevelArgs& a, dim3 grid, hipStream_t s) {
   const bool step1 = a.src != nullptr, look = a.vnext != nullptr, own = a.gamma_out != nullptr;
   if (step1) {
-    if (look) level_kernel<T, VW, true, true, false, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
-    else level_kernel<T, VW, true, false, false, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
+    if (look) level_kernel<T, VW, true, true, false, MULTI, STREAM><<<grid, LV_THREADS, 0, s>>>(a);
+    else level_kernel<T, VW, true, false, false, MULTI, STREAM><<<grid, LV_THREADS, 0, s>>>(a);
   } else if (own) {
-    if (look) level_kernel<T, VW, false, true, true, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
-    else level_kernel<T, VW, false, false, true, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
+    if (look) level_kernel<T, VW, false, true, true, MULTI, STREAM><<<grid, LV_THREADS, 0, s>>>(a);
+    else level_kernel<T, VW, false, false, true, MULTI, STREAM><<<grid, LV_THREADS, 0, s>>>(a);
   } else {
-    if (look) level_kernel<T, VW, false, true, false, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
-    else level_kernel<T, VW, false, false, false, MULTI><<<grid, LV_THREADS, 0, s>>>(a);
+    if (look) level_kernel<T, VW, false, true, false, MULTI, STREAM><<<grid, LV_THREADS, 0, s>>>(a);
+    else level_kernel<T, VW, false, false, false, MULTI, STREAM><<<grid, LV_THREADS, 0, s>>>(a);
   }
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
+
+// Last-level (infinity) cache of the MI355X: 256 MiB. A launch whose active
+// columns exceed it streams them with non-temporal accesses.
+constexpr double kLvMallBytes = 256.0 * 1024.0 * 1024.0;
 
 template <typename T, int VW>
 enkf_status launch_t(const LevelArgs& a, hipStream_t s) {
@@ -300,8 +310,11 @@ enkf_status launch_t(const LevelArgs& a, hipStream_t s) {
   const int ng = (a.m + LV_COLS - 1) / LV_COLS;
   if (nb > 0x7fffffff || ng > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "level sweep: problem too large for grid");
   const int64_t rpb = (int64_t)LV_THREADS * VW * LV_RPT;
-  if (nb < (a.n + rpb - 1) / rpb) return launch_flags<T, VW, true>(a, dim3((unsigned)nb, (unsigned)ng), s);
-  return launch_flags<T, VW, false>(a, dim3((unsigned)nb, (unsigned)ng), s);
+  const dim3 grid((unsigned)nb, (unsigned)ng);
+  const bool stream = (double)a.m * (double)a.n * sizeof(T) > kLvMallBytes;
+  if (nb < (a.n + rpb - 1) / rpb)
+    return stream ? launch_flags<T, VW, true, true>(a, grid, s) : launch_flags<T, VW, true, false>(a, grid, s);
+  return stream ? launch_flags<T, VW, false, true>(a, grid, s) : launch_flags<T, VW, false, false>(a, grid, s);
 }
 
 }  // namespace

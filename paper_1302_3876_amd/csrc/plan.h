@@ -9,6 +9,9 @@ namespace enkf {
 
 size_t dtype_size(enkf_dtype d);
 enkf_status validate_desc(const enkf_sm_desc* d);
+// Panel widths the tuner times for n_ens = N: 32, 64, 96, 128 up to N (N itself below 32).
+std::vector<int> tune_candidates(int N);
+constexpr int kMaxTune = 4;
 
 // Slots of Plan::norms (device, FP64).
 enum NormSlot : int {
@@ -42,6 +45,10 @@ struct Plan {
   char* Bt = nullptr;           // converted right factor of the nn products
   // blocked
   int block = 0;                // panel width b
+  bool autotune = false;        // ENKF_FLAG_AUTOTUNE with block 0: width timed at init (tune_block)
+  int ntune = 0;                // widths the tuner timed and their factor + solve times
+  int tune_b[kMaxTune] = {};
+  float tune_ms[kMaxTune] = {};
   int npanel = 0;
   double* Sfac = nullptr;       // npanel x (b x b) S = D^{-1/2} L^{-1} of M = L D L^T
   double* Pbuf = nullptr;       // b x (N + max_nrhs) panel products
@@ -80,6 +87,7 @@ struct Plan {
 
   enkf_status create(const enkf_sm_desc& d, const double* r, const void* V, int64_t ldv, hipStream_t s);
   enkf_status factor();
+  enkf_status tune_block();
   // ENKF_FLAG_DIAGNOSE: ||W||_2 estimate after a factorisation; after a
   // synchronous solve, the residual (if the form has none), ||Z|| and eta.
   enkf_status diag_factor();

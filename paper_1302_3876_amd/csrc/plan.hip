@@ -5,6 +5,10 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
 
 #include "diag.h"
 #include "gemm_lowp.h"
@@ -81,12 +85,15 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   diagnose = (d.flags & ENKF_FLAG_DIAGNOSE) != 0 && d.dtype == ENKF_F64 && N <= wnorm_max_n_ens();
   wdt = mixed ? ENKF_F32 : d.dtype;
   const size_t wes = dtype_size(wdt);
+  autotune = blocked && d.block == 0 && (d.flags & ENKF_FLAG_AUTOTUNE) != 0;
+  std::vector<int> widths;      // every panel width the workspace must serve
   if (blocked) {
     block = d.block > 0 ? d.block : std::min(N, kMaxPanel);
     if (block > kMaxPanel) return fail(ENKF_ERR_NOT_SUPPORTED, "init: panel width above 128");
     npanel = (N + block - 1) / block;
     if (d.dtype == ENKF_F32 && d.math != ENKF_MATH_F32)
       return fail(ENKF_ERR_NOT_SUPPORTED, "init: FP32 storage takes FP32 panels (narrower panels refine an FP64 solve)");
+    widths = autotune ? tune_candidates(N) : std::vector<int>{block};
   }
   ldu = (int64_t)align_up((size_t)n, 64);
 
@@ -100,12 +107,17 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
   const size_t oG = take(sizeof(double) * (size_t)N * mcols);
   // split-K partials: the largest over every (a, m) product this plan runs
   int64_t tnp = tn_partial_elems(n, N, N);   // analysis V^T Z
-  if (blocked) {
-    for (int p = 0; p < npanel; ++p) {
-      const int k0 = p * block, bl = std::min(block, N - k0);
+  size_t sfac_elems = 0, pbuf_elems = 0, qbuf_elems = 0;
+  for (const int b : widths) {
+    const int np = (N + b - 1) / b;
+    for (int p = 0; p < np; ++p) {
+      const int k0 = p * b, bl = std::min(b, N - k0);
       tnp = std::max(tnp, tn_partial_elems(n, bl, N - k0));
       for (int m = 1; m <= max_nrhs; ++m) tnp = std::max(tnp, tn_partial_elems(n, bl, m));
     }
+    sfac_elems = std::max(sfac_elems, (size_t)np * b * b);
+    pbuf_elems = std::max(pbuf_elems, (size_t)b * (N + mcols));
+    qbuf_elems = std::max(qbuf_elems, (size_t)b * mcols);
   }
   if (mixed || refine64 || diagnose)
     for (int m = 1; m <= max_nrhs; ++m) tnp = std::max(tnp, tn_partial_elems(n, N, m));
@@ -126,9 +138,9 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
       oAct = take(sizeof(int32_t) * 2 * (size_t)(N + max_nrhs));
     }
   } else {
-    oSfac = take(sizeof(double) * (size_t)npanel * block * block);
-    oPbuf = take(sizeof(double) * (size_t)block * (N + mcols));
-    oQbuf = take(sizeof(double) * (size_t)block * mcols);
+    oSfac = take(sizeof(double) * sfac_elems);
+    oPbuf = take(sizeof(double) * pbuf_elems);
+    oQbuf = take(sizeof(double) * qbuf_elems);
   }
   if (mixed) {
     oVw = take((size_t)ldu * N * sizeof(float));
@@ -226,6 +238,108 @@ enkf_status Plan::block_step1(enkf_dtype dt, int m, const void* X, int64_t ldx, 
   TimedLaunch tl(&timing, stream, KC_STEP1, 2.0 * (double)desc.n_obs * m * dtype_size(dt),
                  2.0 * (double)desc.n_obs * m * max_bs);
   return launch_block_solve(dt, max_bs, nblk, m, boff, bpoff, Lf, X, ldx, Y, ldy, stream);
+}
+
+// ------------------------------------------------------------------ panel width
+std::vector<int> tune_candidates(int N) {
+  std::vector<int> c;
+  for (const int b : {32, 64, 96, 128})
+    if (b <= N) c.push_back(b);
+  if (c.empty()) c.push_back(N);
+  return c;
+}
+
+namespace {
+struct TuneKey {
+  int64_t n;
+  int N, dtype, math, nrhs, block_r;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(n, N, dtype, math, nrhs, block_r) < std::tie(o.n, o.N, o.dtype, o.math, o.nrhs, o.block_r);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;   // panel width picked per shape, for the life of the process
+}  // namespace
+
+// ENKF_FLAG_AUTOTUNE: time the factorisation and one solve of min(N,
+// max_nrhs) right-hand sides (the columns of V, without refinement) for each
+// candidate width on this plan's own data, and keep the fastest. A shape
+// tuned before in this process reuses its width.
+enkf_status Plan::tune_block() {
+  if (!autotune) return ENKF_SUCCESS;
+  const TuneKey key{desc.n_obs, desc.n_ens, (int)desc.dtype, (int)desc.math, max_nrhs, block_r ? 1 : 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      block = it->second;
+      npanel = (desc.n_ens + block - 1) / block;
+      return ENKF_SUCCESS;
+    }
+  }
+  const int64_t n = desc.n_obs;
+  const int N = desc.n_ens;
+  const int nr = std::min(N, max_nrhs);
+  const std::vector<int> cand = tune_candidates(N);
+  void* scratch = nullptr;
+  if (!mixed) {
+    if (hipMalloc(&scratch, (size_t)ldu * nr * dtype_size(wdt)) != hipSuccess)
+      return fail(ENKF_ERR_OUT_OF_MEMORY, "autotune: right-hand side scratch");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  enkf_status st = ENKF_SUCCESS;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(ENKF_ERR_HIP, "autotune: events");
+  ntune = 0;
+  int best = cand[0];
+  float best_ms = 0.f;
+  for (size_t ci = 0; ci < cand.size() && st == ENKF_SUCCESS; ++ci) {
+    block = cand[ci];
+    npanel = (N + block - 1) / block;
+    float tmin = 0.f;
+    for (int rep = 0; rep < 3 && st == ENKF_SUCCESS; ++rep) {   // rep 0 warms up
+      if (mixed) st = launch_convert(n, nr, static_cast<const double*>(V), ldv, static_cast<float*>(Zw), ldu, nullptr,
+                                     r, status, stream);
+      if (st != ENKF_SUCCESS) break;
+      if (hipEventRecord(e0, stream) != hipSuccess) { st = fail(ENKF_ERR_HIP, "autotune: event record"); break; }
+      st = factor_blocked();
+      if (st == ENKF_SUCCESS)
+        st = mixed ? solve_blocked(nr, Zw, ldu, Zw, ldu, true) : solve_blocked(nr, V, ldv, scratch, ldu);
+      if (st != ENKF_SUCCESS) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(ENKF_ERR_HIP, "autotune: event timing");
+        break;
+      }
+      if (rep == 1 || (rep > 1 && ms < tmin)) tmin = ms;
+    }
+    if (st != ENKF_SUCCESS) break;
+    if (ntune < kMaxTune) {
+      tune_b[ntune] = cand[ci];
+      tune_ms[ntune] = tmin;
+      ++ntune;
+    }
+    if (ci == 0 || tmin < best_ms) {
+      best = cand[ci];
+      best_ms = tmin;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (scratch) {
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(scratch);
+  }
+  if (st != ENKF_SUCCESS) return st;
+  block = best;
+  npanel = (N + block - 1) / block;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = block;
+  }
+  // the trial factorisations may have latched a status; the real one
+  // that follows latches it again
+  return clear_status();
 }
 
 enkf_status Plan::factor() {
@@ -806,7 +920,7 @@ enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z
   const int N = desc.n_ens;
   enkf_status st;
   {
-    TimedLaunch tl(&timing, stream, KC_RESIDUAL, (double)(N + nrhs) * n * 8.0, 2.0 * n * N * nrhs);
+    TimedLaunch tl(&timing, stream, KC_RESIDUAL_TN, (double)(N + nrhs) * n * 8.0, 2.0 * n * N * nrhs);
     st = launch_tn(ENKF_F64, n, N, nrhs, V, ldv, Z, ldz, G, N, tn_part, stream);
     if (st != ENKF_SUCCESS) return st;
   }
@@ -929,6 +1043,7 @@ enkf_status Plan::get_info(enkf_sm_info* info) {
   out.gamma_max = *std::max_element(g.begin(), g.end());
   out.device_status = (int32_t)st;
   out.hip_error = (int32_t)hipPeekAtLastError();
+  out.block = desc.algo == ENKF_SM_BLOCKED ? block : 1;
   *info = out;
   if (st != 0)
     return fail(static_cast<enkf_status>(st), "a kernel latched an error (r_i or gamma_k not finite or not > 0)");

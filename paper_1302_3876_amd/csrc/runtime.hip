@@ -97,7 +97,8 @@ enkf_status validate_desc(const enkf_sm_desc* d) {
   if (d->dtype != ENKF_F64 && d->dtype != ENKF_F32) return fail(ENKF_ERR_INVALID_ARG, "unknown dtype");
   if (d->algo != ENKF_SM_PLAIN && d->algo != ENKF_SM_BLOCKED) return fail(ENKF_ERR_INVALID_ARG, "unknown algo");
   if (d->math < ENKF_MATH_F64 || d->math > ENKF_MATH_F16X2) return fail(ENKF_ERR_INVALID_ARG, "unknown math");
-  if (d->flags & ~(ENKF_FLAG_PIVOT | ENKF_FLAG_DIAGNOSE)) return fail(ENKF_ERR_INVALID_ARG, "unknown flag bits");
+  if (d->flags & ~(ENKF_FLAG_PIVOT | ENKF_FLAG_DIAGNOSE | ENKF_FLAG_AUTOTUNE))
+    return fail(ENKF_ERR_INVALID_ARG, "unknown flag bits");
   if (d->max_nrhs < 0) return fail(ENKF_ERR_INVALID_ARG, "max_nrhs must be >= 0");
   if (d->refine_max_iter < 0) return fail(ENKF_ERR_INVALID_ARG, "refine_max_iter must be >= 0");
   if (!(d->refine_tol >= 0.0)) return fail(ENKF_ERR_INVALID_ARG, "refine_tol must be >= 0");
@@ -154,7 +155,8 @@ enkf_status enkf_sm_init(enkf_sm_plan* out, const enkf_sm_desc* desc, const doub
     delete p;
     return st;
   }
-  st = p->factor();
+  st = p->tune_block();
+  if (st == ENKF_SUCCESS) st = p->factor();
   if (st != ENKF_SUCCESS) {
     delete p;
     return st;
@@ -187,6 +189,7 @@ enkf_status enkf_sm_init_block_r(enkf_sm_plan* out, const enkf_sm_desc* desc, co
   st = p->create(*desc, nullptr, V, ldv, static_cast<hipStream_t>(stream));
   if (st == ENKF_SUCCESS) st = p->set_block_r(R->n_blocks, R->offsets);
   if (st == ENKF_SUCCESS) st = p->factor_block_r(R->blocks);
+  if (st == ENKF_SUCCESS) st = p->tune_block();
   if (st == ENKF_SUCCESS) st = p->factor();
   if (st != ENKF_SUCCESS) {
     delete p;
@@ -352,6 +355,17 @@ enkf_status enkf_analysis_ex(enkf_sm_plan plan, int64_t n_state, enkf_dtype x_dt
 enkf_status enkf_sm_get_info(enkf_sm_plan plan, enkf_sm_info* info) {
   if (!plan || !info) return fail(ENKF_ERR_INVALID_ARG, "get_info: NULL argument");
   return reinterpret_cast<Plan*>(plan)->get_info(info);
+}
+
+enkf_status enkf_sm_get_tuning(enkf_sm_plan plan, int32_t* widths, double* ms, int32_t* count) {
+  if (!plan || !count) return fail(ENKF_ERR_INVALID_ARG, "get_tuning: NULL argument");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  *count = p->ntune;
+  for (int i = 0; i < p->ntune; ++i) {
+    if (widths) widths[i] = p->tune_b[i];
+    if (ms) ms[i] = p->tune_ms[i];
+  }
+  return ENKF_SUCCESS;
 }
 
 enkf_status enkf_sm_get_pivots(enkf_sm_plan plan, double* gamma_host, int32_t* perm_host) {

@@ -26,11 +26,11 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "enkf_sm.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(enkf_sm_desc),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(enkf_sm_desc),"
         " offsetof(enkf_sm_desc, refine_tol), offsetof(enkf_sm_desc, flags), sizeof(enkf_sm_info),"
         " offsetof(enkf_sm_info, rel_residual), offsetof(enkf_sm_info, backward_error),"
         " offsetof(enkf_sm_info, gamma_max), offsetof(enkf_sm_info, device_status),"
-        " offsetof(enkf_sm_info, hip_error)); printf(\"%zu %zu\\n\", sizeof(enkf_block_r),"
+        " offsetof(enkf_sm_info, hip_error), offsetof(enkf_sm_info, block)); printf(\"%zu %zu\\n\", sizeof(enkf_block_r),"
         " offsetof(enkf_block_r, blocks)); return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -38,6 +38,7 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     want = [ctypes.sizeof(pk.SmDesc), pk.SmDesc.refine_tol.offset, pk.SmDesc.flags.offset,
             ctypes.sizeof(pk.SmInfo), pk.SmInfo.rel_residual.offset, pk.SmInfo.backward_error.offset,
             pk.SmInfo.gamma_max.offset, pk.SmInfo.device_status.offset, pk.SmInfo.hip_error.offset,
+            pk.SmInfo.block.offset,
             ctypes.sizeof(pk.BlockR), pk.BlockR.blocks.offset]
     assert [int(x) for x in got] == want
 
@@ -56,6 +57,7 @@ def test_validate_desc_accepts_good():
     assert pk.enkf_sm_validate_desc(_desc(n_obs=1, n_ens=1)) == 0
     assert pk.enkf_sm_validate_desc(_desc(flags=pk.ENKF_FLAG_DIAGNOSE)) == 0
     assert pk.enkf_sm_validate_desc(_desc(algo=pk.ENKF_SM_BLOCKED, flags=pk.ENKF_FLAG_DIAGNOSE)) == 0
+    assert pk.enkf_sm_validate_desc(_desc(algo=pk.ENKF_SM_BLOCKED, flags=pk.ENKF_FLAG_AUTOTUNE)) == 0
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -85,6 +87,7 @@ def test_null_arguments_rejected_without_gpu():
     assert lib.enkf_sm_factor_solve(None, None, None, 1, 1, None, 1, None, 1, None) == 1
     assert lib.enkf_sm_init_block_r(ctypes.byref(h), ctypes.byref(_desc()), None, None, 100, None) == 1
     assert lib.enkf_sm_refactor_block_r(None, None, None, 100) == 1
+    assert lib.enkf_sm_get_tuning(None, None, None, None) == 1
     assert lib.enkf_analysis(None, 1, None, 1, None, 1, None, 1) == 1
     assert lib.enkf_build_vd(10, 1, 0, None, 10, None, 5, None, None, 5, None, None, 5, None) == 1
     assert lib.enkf_build_vd(10, 4, 0, None, 10, None, 5, None, None, 5, None, None, 5, None) == 1

@@ -31,5 +31,13 @@ def test_multi_rank_launch_is_refused():
 def test_help_lists_workloads():
     r = _run(["--help"])
     assert r.returncode == 0
-    for w in ("c2", "c3", "c4", "c5", "loc", "cycle"):
+    for w in ("c1", "c2", "c3", "c4", "c5", "loc", "cycle"):
         assert w in r.stdout
+
+
+def test_form_spec_parses_panel_width():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.form_spec("mixed_f32@64") == ("mixed_f32", 64)
+    assert bench.form_spec("blocked_f64") == ("blocked_f64", 0)
+    assert all(bench.form_spec(f)[0] in bench.FORMS for f in bench.DEFAULT_FORMS["c3"])

@@ -332,3 +332,28 @@ def test_diagnose_flag_reports_backward_error(algo, math, refine):
     plain = pk.Plan(dev(w.r), dev(Vo))
     _, info3 = plain.solve(dev(Do), info=True)
     assert info3["backward_error"] == -1.0 and info3["rel_residual"] == -1.0
+
+
+@pytest.mark.parametrize("math", ["f64", "f32"])
+def test_autotuned_panel_width(math):
+    """ENKF_FLAG_AUTOTUNE with block 0: init times each candidate width (32,
+    64, 96, 128 up to N) on the plan's data and keeps the fastest; the solve
+    with it matches the oracle; a second plan of the same shape reuses the
+    width without timing again."""
+    import torch
+    pk = _pk()
+    n, N = 40000, 100
+    w = synth.direct_vd_workload("c3-small", n, N, seed=6100)
+    kw = dict(algo="blocked", math=math, autotune=True)
+    if math != "f64":
+        kw.update(refine_max_iter=8, refine_tol=1e-11)
+    plan = pk.Plan(dev(w.r), dev(w.V), **kw)
+    tun = plan.tuning()
+    Z, info = plan.solve(dev(w.D), info=True)
+    torch.cuda.synchronize()
+    print(math, tun, info, flush=True)
+    assert sorted(tun) == [32, 64, 96] and all(v > 0 for v in tun.values())
+    assert info["block"] == min(tun, key=tun.get)
+    fp64_gate(w.r, w.V, w.D, host(Z), oracle.sm_solve(w.r, w.V, w.D)["Z"])
+    plan2 = pk.Plan(dev(w.r), dev(w.V), **kw)
+    assert plan2.tuning() == {} and plan2.info()["block"] == info["block"]
