@@ -312,6 +312,32 @@ enkf_status enkf_sm_get_timing(enkf_sm_plan plan, int32_t kernel_class, double* 
 void enkf_sm_destroy(enkf_sm_plan plan);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work of
+ * enkf_sm_init followed by enkf_sm_factor_solve on the same arguments, with
+ * the same kernels and launch sequence (so the same Z, bit for bit), but the
+ * plan's workspace carved from a static device array of
+ * ENKF_NOALLOC_SCRATCH_BYTES on each GPU the library runs on, held until the
+ * process ends, instead of hipMalloc. No device memory is allocated or freed.
+ *   desc, r, V, ldv: as enkf_sm_init (ENKF_FLAG_AUTOTUNE is refused: the
+ *     tuner allocates; block-diagonal R is not available here);
+ *   nrhs, D, ldd, Z, ldz, info: as enkf_sm_factor_solve (info != NULL
+ *     synchronises `stream` and reports; NULL only enqueues);
+ *   stream: hipStream_t as void* (NULL: the null stream).
+ * A problem whose workspace (U: n_obs x (n_ens + max_nrhs) in the storage
+ * type for the plain algorithm, plus panel and reduction buffers) exceeds
+ * the scratch returns ENKF_ERR_NOT_SUPPORTED with the needed size in
+ * enkf_last_error_message(). Every call on a GPU shares that GPU's scratch:
+ * calls that overlap in time on one GPU (different streams, or host threads)
+ * race and give wrong results; calls on one stream are ordered and safe.
+ * The factor lives in the scratch only until the next call.
+ */
+#define ENKF_NOALLOC_SCRATCH_BYTES (64u << 20)
+enkf_status enkf_sm_solve_noalloc(const enkf_sm_desc* desc, const double* r, const void* V, int64_t ldv,
+                                  int32_t nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz,
+                                  enkf_sm_info* info, void* stream);
+
+/*
  * Measured matrix-core throughput of the current device, the on-box
  * counterpart of the published peaks the rooflines divide by (MI355X dense:
  * FP64 78.6, FP32 157.3, BF16/FP16 2500 TFLOP/s). Runs a kernel in which

@@ -89,6 +89,8 @@ def lib():
     L.enkf_sm_get_info.argtypes = [vp, ctypes.POINTER(SmInfo)]
     L.enkf_sm_get_pivots.argtypes = [vp, vp, vp]
     L.enkf_sm_get_tuning.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
+    L.enkf_sm_solve_noalloc.argtypes = [ctypes.POINTER(SmDesc), vp, vp, i64, i32, vp, i64, vp, i64,
+                                        ctypes.POINTER(SmInfo), vp]
     L.enkf_sm_set_timing.argtypes = [vp, i32]
     L.enkf_sm_get_timing.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                      ctypes.POINTER(dbl)]
@@ -109,7 +111,7 @@ def lib():
     L.enkf_last_error_message.restype = ctypes.c_char_p
     for name in ("enkf_sm_validate_desc", "enkf_build_vd", "enkf_sm_init", "enkf_sm_init_block_r", "enkf_sm_refactor",
                  "enkf_sm_refactor_block_r", "enkf_sm_factor_solve", "enkf_sm_solve", "enkf_analysis",
-                 "enkf_analysis_ex", "enkf_localized_analysis", "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_get_tuning", "enkf_sm_set_timing", "enkf_sm_get_timing",
+                 "enkf_analysis_ex", "enkf_localized_analysis", "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_get_tuning", "enkf_sm_solve_noalloc", "enkf_sm_set_timing", "enkf_sm_get_timing",
                  "enkf_local_init", "enkf_local_analysis", "enkf_local_sync"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -398,6 +400,30 @@ def enkf_sm_solve(plan: Plan, D, Z=None, info: bool = False):
 
 def enkf_analysis(plan: Plan, XB, Z, XA=None):
     return plan.analysis(XB, Z, XA)
+
+
+def enkf_sm_solve_noalloc(r, V, D, Z=None, algo: str = "plain", math: Optional[str] = None, block: int = 0,
+                          refine_max_iter: int = 0, refine_tol: float = 0.0, info: bool = False):
+    """Factor and solve in one call with the workspace in the library's
+    static device scratch: no device allocation (enkf_sm_solve_noalloc).
+    Returns Z (and the info dict when info=True)."""
+    torch = _torch()
+    dt = _dtype_code(V)
+    if math is None:
+        math = "f64" if dt == ENKF_F64 else "f32"
+    pV, ldv = _mat(V, "V", dt)
+    pD, ldd = _mat(D, "D", dt)
+    if Z is None:
+        Z = colmajor(D.shape[0], D.shape[1], D.dtype, D.device)
+    pZ, ldz = _mat(Z, "Z", dt)
+    n, N = V.shape
+    desc = SmDesc(n, N, dt, ENKF_SM_PLAIN if algo == "plain" else ENKF_SM_BLOCKED, MATH[math], block,
+                  max(D.shape[1], 1) if D.shape[1] > N else 0, refine_max_iter, refine_tol, 0)
+    inf = SmInfo() if info else None
+    _check(lib().enkf_sm_solve_noalloc(ctypes.byref(desc), _vec(r, "r", torch.float64), pV, ldv, D.shape[1], pD, ldd,
+                                       pZ, ldz, ctypes.byref(inf) if info else None, _stream()),
+           "enkf_sm_solve_noalloc")
+    return (Z, inf.as_dict()) if info else Z
 
 
 class LocalPlan:

@@ -9,6 +9,11 @@ namespace enkf {
 
 size_t dtype_size(enkf_dtype d);
 enkf_status validate_desc(const enkf_sm_desc* d);
+struct Plan;
+// Refuses an overlap of Z with D that the plan's solve cannot take (refined
+// and mixed solves: any overlap; others: anything but in place).
+enkf_status check_rhs_overlap(const Plan* p, const char* where, int32_t nrhs, const void* D, int64_t ldd,
+                              const void* Z, int64_t ldz);
 // Panel widths the tuner times for n_ens = N: 32, 64, 96, 128 up to N (N itself below 32).
 std::vector<int> tune_candidates(int N);
 constexpr int kMaxTune = 4;
@@ -35,6 +40,7 @@ struct Plan {
   // workspace (one allocation, carved into the pieces below)
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  bool owns_ws = false;         // false: a borrowed workspace (not freed, no wait at destruction)
   void* U = nullptr;            // plain factor: column k = u_k^{(k-1)}; then max_nrhs columns of Z (fused)
   int64_t ldu = 0;
   double* gamma = nullptr;      // N pivots
@@ -85,7 +91,10 @@ struct Plan {
   Timing timing;
   enkf_sm_info last{};
 
-  enkf_status create(const enkf_sm_desc& d, const double* r, const void* V, int64_t ldv, hipStream_t s);
+  // ext_ws: carve the workspace from this device buffer of ext_bytes (fails
+  // with NOT_SUPPORTED when it does not fit) instead of allocating it
+  enkf_status create(const enkf_sm_desc& d, const double* r, const void* V, int64_t ldv, hipStream_t s,
+                     char* ext_ws = nullptr, size_t ext_bytes = 0);
   enkf_status factor();
   enkf_status tune_block();
   // ENKF_FLAG_DIAGNOSE: ||W||_2 estimate after a factorisation; after a

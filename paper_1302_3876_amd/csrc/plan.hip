@@ -62,7 +62,8 @@ enkf_status Plan::panel_nn(const NnArgs& a) {
   return launch_nn(wdt, NN_UPDATE, a, stream);
 }
 
-enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_, int64_t ldv_, hipStream_t s) {
+enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_, int64_t ldv_, hipStream_t s,
+                         char* ext_ws, size_t ext_bytes) {
   desc = d;
   r = r_;
   V = V_;
@@ -153,10 +154,20 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
     oResPart = take(sizeof(double) * (size_t)res_part_cap);
   }
   ws_bytes = off;
-  hipError_t e = hipMalloc(&ws, ws_bytes);
-  if (e != hipSuccess) {
-    ws = nullptr;
-    return fail(ENKF_ERR_OUT_OF_MEMORY, "init: workspace of " + std::to_string(ws_bytes) + " bytes");
+  if (ext_ws) {
+    // the caller's workspace (the static scratch of the allocation-free call)
+    if (ws_bytes > ext_bytes)
+      return fail(ENKF_ERR_NOT_SUPPORTED, "workspace of " + std::to_string(ws_bytes) + " bytes exceeds the " +
+                                              std::to_string(ext_bytes) + "-byte static scratch");
+    ws = ext_ws;
+    owns_ws = false;
+  } else {
+    hipError_t e = hipMalloc(&ws, ws_bytes);
+    if (e != hipSuccess) {
+      ws = nullptr;
+      return fail(ENKF_ERR_OUT_OF_MEMORY, "init: workspace of " + std::to_string(ws_bytes) + " bytes");
+    }
+    owns_ws = true;
   }
   U = ws + oU;
   gamma = reinterpret_cast<double*>(ws + oGamma);
@@ -190,15 +201,20 @@ enkf_status Plan::create(const enkf_sm_desc& d, const double* r_, const void* V_
     norms = reinterpret_cast<double*>(ws + oNorm);
     res_part = reinterpret_cast<double*>(ws + oResPart);
   }
-  ENKF_HIP_CHECK(hipMemsetAsync(ws + oStat, 0, sizeof(unsigned) * 4, stream));
+  // the status words start at zero (a fill kernel: valid under stream capture)
+  clear_words_kernel<<<1, 64, 0, stream>>>(status, 4);
+  ENKF_HIP_CHECK(hipGetLastError());
   last.rel_residual = -1.0;
   last.backward_error = -1.0;
   return ENKF_SUCCESS;
 }
 
 Plan::~Plan() {
+  // a plan on a borrowed workspace neither waits nor frees: its kernels
+  // reference no host state of the plan
+  if (!owns_ws && !bws) return;
   if (stream || ws || bws) (void)hipStreamSynchronize(stream);
-  if (ws) (void)hipFree(ws);
+  if (ws && owns_ws) (void)hipFree(ws);
   if (bws) (void)hipFree(bws);
 }
 
@@ -1036,11 +1052,18 @@ enkf_status Plan::get_info(enkf_sm_info* info) {
   unsigned st = 0;
   enkf_status e = read_status(&st);
   if (e != ENKF_SUCCESS) return e;
-  std::vector<double> g(desc.n_ens);
-  ENKF_HIP_CHECK(hipMemcpy(g.data(), gamma, sizeof(double) * desc.n_ens, hipMemcpyDeviceToHost));
   enkf_sm_info out = last;
-  out.gamma_min = *std::min_element(g.begin(), g.end());
-  out.gamma_max = *std::max_element(g.begin(), g.end());
+  out.gamma_min = std::numeric_limits<double>::infinity();
+  out.gamma_max = -std::numeric_limits<double>::infinity();
+  double g[256];   // the pivots, a chunk at a time (no host allocation)
+  for (int k0 = 0; k0 < desc.n_ens; k0 += 256) {
+    const int cnt = std::min(256, desc.n_ens - k0);
+    ENKF_HIP_CHECK(hipMemcpy(g, gamma + k0, sizeof(double) * cnt, hipMemcpyDeviceToHost));
+    for (int k = 0; k < cnt; ++k) {
+      out.gamma_min = std::min(out.gamma_min, g[k]);
+      out.gamma_max = std::max(out.gamma_max, g[k]);
+    }
+  }
   out.device_status = (int32_t)st;
   out.hip_error = (int32_t)hipPeekAtLastError();
   out.block = desc.algo == ENKF_SM_BLOCKED ? block : 1;

@@ -115,6 +115,23 @@ enkf_status validate_desc(const enkf_sm_desc* d) {
   return ENKF_SUCCESS;
 }
 
+// D and Z of a solve: the plain and the unrefined blocked solves run in
+// place (Z == D with the same leading dimension); the refined and mixed
+// solves read D again for every residual, so they need it untouched and take
+// no overlap at all. Any other overlap of the two column ranges is refused.
+enkf_status check_rhs_overlap(const Plan* p, const char* where, int32_t nrhs, const void* D, int64_t ldd,
+                              const void* Z, int64_t ldz) {
+  const size_t es = dtype_size(p->desc.dtype);
+  const uintptr_t d0 = (uintptr_t)D, d1 = d0 + ((size_t)ldd * (nrhs - 1) + p->desc.n_obs) * es;
+  const uintptr_t z0 = (uintptr_t)Z, z1 = z0 + ((size_t)ldz * (nrhs - 1) + p->desc.n_obs) * es;
+  if (!(z0 < d1 && d0 < z1)) return ENKF_SUCCESS;
+  if (p->mixed || p->refine64)
+    return fail(ENKF_ERR_INVALID_ARG, std::string(where) + ": Z overlaps D, and a refined solve reads D after writing Z");
+  if (D != Z || ldd != ldz)
+    return fail(ENKF_ERR_INVALID_ARG, std::string(where) + ": Z overlaps D other than in place with the same leading dimension");
+  return ENKF_SUCCESS;
+}
+
 }  // namespace enkf
 
 using namespace enkf;
@@ -224,23 +241,6 @@ enkf_status enkf_sm_refactor(enkf_sm_plan plan, const double* r, const void* V, 
   enkf_status st = p->clear_status();
   if (st != ENKF_SUCCESS) return st;
   return p->factor();
-}
-
-// D and Z of a solve: the plain and the unrefined blocked solves run in
-// place (Z == D with the same leading dimension); the refined and mixed
-// solves read D again for every residual, so they need it untouched and take
-// no overlap at all. Any other overlap of the two column ranges is refused.
-static enkf_status check_rhs_overlap(const Plan* p, const char* where, int32_t nrhs, const void* D, int64_t ldd,
-                                     const void* Z, int64_t ldz) {
-  const size_t es = dtype_size(p->desc.dtype);
-  const uintptr_t d0 = (uintptr_t)D, d1 = d0 + ((size_t)ldd * (nrhs - 1) + p->desc.n_obs) * es;
-  const uintptr_t z0 = (uintptr_t)Z, z1 = z0 + ((size_t)ldz * (nrhs - 1) + p->desc.n_obs) * es;
-  if (!(z0 < d1 && d0 < z1)) return ENKF_SUCCESS;
-  if (p->mixed || p->refine64)
-    return fail(ENKF_ERR_INVALID_ARG, std::string(where) + ": Z overlaps D, and a refined solve reads D after writing Z");
-  if (D != Z || ldd != ldz)
-    return fail(ENKF_ERR_INVALID_ARG, std::string(where) + ": Z overlaps D other than in place with the same leading dimension");
-  return ENKF_SUCCESS;
 }
 
 enkf_status enkf_sm_solve(enkf_sm_plan plan, int32_t nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz,
