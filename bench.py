@@ -601,6 +601,20 @@ def run_c5(w, args, pk, torch):
             fn()
         return timed_steps(torch, fn, steps)
 
+    only = [f for f in args.forms.split(",") if f]
+    if only:
+        # just the analysis product on FP32 / narrow inputs (for profiling):
+        # Z from one FP32 blocked solve
+        pz = pk.Plan(r, V32, algo="blocked", block=args.block)
+        pz.solve(D32, Z32)
+        an = {}
+        for f in only:
+            math = f.replace("analysis_", "")
+            ms = timed(lambda: pz.analysis_ex(XB, Z32, XA, math=math), max(2, args.steps))[0]
+            an[math] = {"ms": round(ms, 3), "TFLOP/s_incl_VtZ": round(2.0 * w.n_state * N * N / (ms * 1e-3) / 1e12, 2)}
+            print(f"[bench] c5 analysis {math}: {ms:.3f} ms", file=sys.stderr, flush=True)
+        pz.close()
+        return {"analysis_product": an}
     # (a) FP32 blocked, build + factor + solve + analysis (FP32)
     pa = pk.Plan(r, V32, algo="blocked", block=args.block)
 
@@ -831,6 +845,9 @@ def main():
         w = synth.c5()
         print(f"[bench] c5 inputs generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
         res = run_c5(w, args, pk, torch)
+        if "mixed_f32" not in res:
+            print(json.dumps({"metric": METRIC, "config": {"name": "c5", "forms": args.forms}, "forms": res}), flush=True)
+            return
         head = res["mixed_f32"]
         k = head["kernels"]["gram"]
         ach = k["TFLOP/s"]

@@ -32,6 +32,15 @@ constexpr int LV_THREADS = 256;
 constexpr int LV_WAVES = LV_THREADS / kWave;
 constexpr int LV_COLS = 8;
 constexpr int LV_RPT = 2;
+// Streamed launches (columns past the last-level cache): half the columns
+// per block and twice the rows, so fewer column streams are open at once
+// (n = 2^21, 512 down to 256 columns per level, per-solve time: 8 x 2 636 ms,
+// 4 x 4 625 ms, 2 x 8 655 ms, 16 x 2 646 ms; narrower groups re-read u_k and
+// v_{k+1} more often).
+constexpr int LV_COLS_STREAM = 4;
+constexpr int LV_RPT_STREAM = 4;
+template <bool STREAM> constexpr int lv_cols() { return STREAM ? LV_COLS_STREAM : LV_COLS; }
+template <bool STREAM> constexpr int lv_rpt() { return STREAM ? LV_RPT_STREAM : LV_RPT; }
 constexpr int64_t kLvMaxRowBlocks = 256;
 
 template <typename T, int VW> struct VecT;
@@ -117,7 +126,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // register budget).
 template <typename T, int VW, bool STEP1, bool LOOKAHEAD, bool OWN_GAMMA, bool MULTI, bool STREAM>
 __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
-  constexpr int COLS = LV_COLS, RPT = LV_RPT;
+  constexpr int COLS = lv_cols<STREAM>(), RPT = lv_rpt<STREAM>();
   constexpr int64_t RPB = (int64_t)LV_THREADS * VW * RPT;   // rows of one tile
   const int64_t n = a.n;
   const int nb = gridDim.x;
@@ -307,11 +316,12 @@ template <typename T, int VW>
 enkf_status launch_t(const LevelArgs& a, hipStream_t s) {
   if (a.m <= 0) return ENKF_SUCCESS;
   const int64_t nb = level_row_blocks(ENKF_F64, VW, a.n);
-  const int ng = (a.m + LV_COLS - 1) / LV_COLS;
-  if (nb > 0x7fffffff || ng > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "level sweep: problem too large for grid");
-  const int64_t rpb = (int64_t)LV_THREADS * VW * LV_RPT;
-  const dim3 grid((unsigned)nb, (unsigned)ng);
   const bool stream = (double)a.m * (double)a.n * sizeof(T) > kLvMallBytes;
+  const int cols = stream ? lv_cols<true>() : lv_cols<false>();
+  const int ng = (a.m + cols - 1) / cols;
+  if (nb > 0x7fffffff || ng > 65535) return fail(ENKF_ERR_NOT_SUPPORTED, "level sweep: problem too large for grid");
+  const int64_t rpb = (int64_t)LV_THREADS * VW * (stream ? lv_rpt<true>() : lv_rpt<false>());
+  const dim3 grid((unsigned)nb, (unsigned)ng);
   if (nb < (a.n + rpb - 1) / rpb)
     return stream ? launch_flags<T, VW, true, true>(a, grid, s) : launch_flags<T, VW, true, false>(a, grid, s);
   return stream ? launch_flags<T, VW, false, true>(a, grid, s) : launch_flags<T, VW, false, false>(a, grid, s);

@@ -73,14 +73,14 @@ def _cycle_inputs(n, N, cycles, nsteps, seed, sd_obs):
 # R^{-1}-sized components of Z outside the ensemble space through (the taper
 # breaks the cancellation S V^T W^{-1} relies on) and the filter diverges, in
 # the oracle as on the device.
-# The blocked form runs only the well-conditioned setting: with R = 0.01^2 the
-# capacitance matrix M = I + V^T R^{-1} V has condition ~3e5 and the Woodbury
-# panel update (not backward stable) moves each analysis increment by ~3e-7
-# relative to the level-by-level formula, which the chaotic forecasts then
-# amplify by ~600 over four cycles: a property of the identity, not a
-# mismatch between device and oracle.
+# The blocked form with R = 0.01^2: the capacitance matrix M = I + V^T R^{-1} V
+# has condition ~3e5; the panels apply M^{-1} through its LDL^T factor (two
+# triangular products), which keeps each analysis within rounding of the
+# level-by-level formula, so the chaotic forecasts (which amplify a
+# difference ~600-fold over four cycles) still end within 1e-6.
 @pytest.mark.parametrize("localize,algo,sd_obs,nsteps", [(False, "plain", 0.01, 20), (True, "plain", 1.0, 5),
-                                                         (True, "blocked", 1.0, 5), (False, "blocked", 1.0, 5)])
+                                                         (True, "blocked", 1.0, 5), (False, "blocked", 1.0, 5),
+                                                         (False, "blocked", 0.01, 20)])
 def test_cycling_filter_matches_oracle(localize, algo, sd_obs, nsteps):
     import torch
     pk = _pk()
@@ -100,3 +100,29 @@ def test_cycling_filter_matches_oracle(localize, algo, sd_obs, nsteps):
     assert np.allclose(rf, rfo, rtol=1e-6) and np.allclose(ra, rao, rtol=1e-6)
     if sd_obs < 0.1:     # observations far more accurate than the forecast
         assert all(a < f for a, f in zip(ra, rf))
+
+
+@pytest.mark.slow
+def test_cycle_bench_configuration_matches_oracle():
+    """The configuration bench.py times for the cycling filter: n_state =
+    n_obs = 1000, N = 1000, R = 0.01^2 I, 20 RK4 steps per cycle, blocked
+    solve with the panel width the library picks, from the same seeded
+    inputs (synth.l96_cycle_inputs); three cycles against the oracle's
+    level-by-level filter."""
+    import torch
+    pk = _pk()
+    import bench
+    c = bench.CYCLE
+    cycles = 3
+    XB, obs, r, truths, ys, Es = synth.l96_cycle_inputs(c["n_state"], c["n_ens"], cycles, c["nsteps"], c["seed"])
+    XBd = dev(XB)
+    ra = []
+    for _, amean in pk.cycle_l96(XBd, dev(obs), [dev(y) for y in ys], [dev(E) for E in Es], dev(r), c["nsteps"],
+                                 algo="blocked"):
+        ra.append(float(np.sqrt(np.mean((host(amean) - truths[len(ra)]) ** 2))))
+    torch.cuda.synchronize()
+    Xo, rfo, rao = oracle.cycle_l96(XB, obs, ys, Es, r, c["nsteps"], truths=truths)
+    err = np.abs(host(XBd) - Xo).max() / np.abs(Xo).max()
+    print({"max_rel_ensemble_diff": err, "rmse_analysis": ra, "oracle": rao}, flush=True)
+    assert err <= 1e-6
+    assert np.allclose(ra, rao, rtol=1e-6)
