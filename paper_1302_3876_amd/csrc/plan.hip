@@ -963,7 +963,10 @@ enkf_status Plan::residual64(int nrhs, const void* D, int64_t ldd, const void* Z
     a.part = res_part;            // ||rho||^2 (the convergence test and the scale
     a.part_cap = res_part_cap;    // of rho) from the kernel's own outputs
     a.sumsq = norms;
-    TimedLaunch tl(&timing, stream, KC_RESIDUAL, (double)(N + 3 * nrhs) * n * 8.0, 2.0 * n * N * nrhs);
+    // bytes: V, Z and D read, rho written in FP64, or R^{-1} rho in FP32 (w32)
+    TimedLaunch tl(&timing, stream, KC_RESIDUAL,
+                   (double)(N + 2 * nrhs) * n * 8.0 + (double)nrhs * n * (w32 ? 4.0 : 8.0) + 8.0 * n,
+                   2.0 * n * N * nrhs);
     st = launch_nn(ENKF_F64, NN_RESIDUAL, a, stream);
     if (st != ENKF_SUCCESS) return st;
   }
