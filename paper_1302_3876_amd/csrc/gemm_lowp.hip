@@ -12,6 +12,8 @@
 //   tn: P = A^T B over n rows, split-K partials (FP64), fixed-order sum;
 //   nn: X <- X - A Bm (UPDATE) and XA <- XB + (XB - xbar 1^T)(s Bm) (ANALYSIS);
 //       the right factor is split into its narrow parts once per call.
+#include <atomic>
+
 #include "enkf_internal.h"
 #include "gemm_lowp.h"
 #include "gemm_mfma.h"
@@ -448,6 +450,197 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
   }
 }
 
+// ---------------------------------------------------------------- analysis, row tile resident
+// X^A = X^B + (X^B - xbar 1^T) (s G) with one-pass 16-bit inputs (BF16 or
+// F16) and K = N <= kResMaxK: a block owns 64 rows of X^B and keeps them,
+// centred and rounded, in the LDS for every output column, so X^B is read
+// from memory for the row means, once more to stage the tile and once for
+// the epilogue's X^B (the last two mostly from the last-level cache), and
+// X^A is written once. 4 waves; wave w computes the 64-column output groups
+// w, w + 4, ... as 4 x 4 MFMA tiles of 16 x 16 over K (64 x 64 per wave),
+// the right factor's fragments coming straight from the L2 two steps ahead
+// of their use, the tile's from the LDS. The MFMA result rows run along the
+// output columns and its columns along the output rows, so each lane group
+// reads and writes 16 consecutive rows of X^B / X^A.
+constexpr int RT_ROWS = 64;
+constexpr int RT_NT = 256;
+constexpr int kResMaxK = 1152;
+
+template <int MATH>
+__global__ __launch_bounds__(RT_NT, 1) void analysis_res_kernel(NnArgs p, const typename Lp<MATH>::e_t* __restrict__ Bp,
+                                                               int ldk) {
+  typedef Lp<MATH> P;
+  typedef typename P::e_t E;
+  typedef typename P::v_t VT;
+  static_assert(P::PARTS == 1, "one-pass inputs only");
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int K = p.K;
+  const int kp = ldk;                              // K padded to 32 (the split factor is zero there)
+  const int lds_ld = kp + 8;                       // row stride of the tile in elements
+  E* As = reinterpret_cast<E*>(lds_raw);
+  __shared__ double mean[RT_ROWS];
+  const float* __restrict__ A = static_cast<const float*>(p.A);
+  const int t = threadIdx.x, l = t % kWave, w = t / kWave;
+  const int64_t row0 = (int64_t)blockIdx.x * RT_ROWS;
+  // Passes 1 and 2 read 16-byte row chunks: thread t takes rows 4 (t % 16)
+  // .. + 3 (clamped; rows past n are not stored) and members t / 16 + 16 q,
+  // sixteen loads in flight, so a block keeps 64 KB of X^B in flight.
+  const int rg = t % 16, mq = t / 16;
+  const int64_t rbase = row0 + 4 * rg;
+  // a 16-byte load where the four rows are inside and aligned; else each row
+  // clamped to the last one (its values are never stored)
+  const bool vec = ((uintptr_t)A % 16) == 0 && (p.lda % 4) == 0 && rbase + 3 < p.n;
+  auto load4 = [&](int kk) -> f4v {
+    const float* col = A + (int64_t)kk * p.lda;
+    if (vec) return *reinterpret_cast<const f4v*>(col + rbase);
+    f4v v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = col[min(rbase + e, p.n - 1)];
+    return v;
+  };
+  // 1. row means over the K members
+  double sum[4] = {0.0, 0.0, 0.0, 0.0};
+  {
+    int kk = mq;
+    for (; kk + 15 * 16 < K; kk += 16 * 16) {
+      f4v x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = load4(kk + 16 * u);
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sum[e] += (double)x[u][e];
+    }
+    for (; kk < K; kk += 16) {
+      const f4v x = load4(kk);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sum[e] += (double)x[e];
+    }
+  }
+  __shared__ double red[16][RT_ROWS];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) red[mq][4 * rg + e] = sum[e];
+  __syncthreads();
+  if (t < RT_ROWS) {
+    double tot = 0.0;
+#pragma unroll
+    for (int z = 0; z < 16; ++z) tot += red[z][t];
+    mean[t] = tot / (double)K;
+  }
+  __syncthreads();
+  // 2. the centred tile, rounded to the input type: chunks of 8 members
+  //    c = mq, mq + 16, ... (members past K are zero), two chunks per pass
+  double mu[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) mu[e] = mean[4 * rg + e];
+  for (int c = mq; c < kp / 8; c += 32) {
+    f4v x[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[h][u] = load4(min(8 * (c + 16 * h) + u, K - 1));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k0 = 8 * (c + 16 * h);
+      if (k0 >= kp) break;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        VT v;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          E part[1];
+          P::conv(k0 + u < K ? (float)((double)x[h][u][e] - mu[e]) : 0.f, part);
+          v[u] = part[0];
+        }
+        *reinterpret_cast<VT*>(&As[(4 * rg + e) * lds_ld + k0]) = v;
+      }
+    }
+  }
+  __syncthreads();
+  // 3. products and epilogue, 64 output columns at a time per wave
+  const float* __restrict__ Cin = static_cast<const float*>(p.Cin);
+  float* __restrict__ Cout = static_cast<float*>(p.Cout);
+  const E* arow[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) arow[j] = As + (16 * j + l % 16) * lds_ld + 8 * (l / 16);
+  const int ngroups = (p.m + 63) / 64;
+  for (int g = w; g < ngroups; g += 4) {
+    const int c0 = 64 * g;
+    const E* bcol[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bcol[i] = Bp + (int64_t)(c0 + 16 * i + l % 16) * ldk + 8 * (l / 16);
+    mf_f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
+    VT b0[4], b1[4], b2[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      b0[i] = ld8<VT>(bcol[i]);
+      b1[i] = ld8<VT>(bcol[i] + min(32, kp - 32));
+    }
+    for (int kk = 0; kk < kp; kk += 32) {
+      const int k2 = min(kk + 64, kp - 32);        // past the end: the last chunk again, unused
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b2[i] = ld8<VT>(bcol[i] + k2);
+      VT ro[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ro[j] = ld8<VT>(arow[j] + kk);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = P::mma(b0[i], ro[j], acc[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        b0[i] = b1[i];
+        b1[i] = b2[i];
+      }
+    }
+    // epilogue: acc[i][j] element r = output (row 16 j + l % 16, column 16 i + 4 (l / 16) + r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float cin[4][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t row = min(row0 + 16 * j + l % 16, p.n - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = min(c0 + 16 * i + 4 * (l / 16) + r, p.m - 1);
+          cin[j][r] = Cin[row + (int64_t)col * p.ldc];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = c0 + 16 * i + 4 * (l / 16) + r;
+          const int64_t row = row0 + 16 * j + l % 16;
+          if (col < p.m && row < p.n)
+            Cout[row + (int64_t)col * p.ldo] = (float)((double)cin[j][r] + (double)acc[i][j][r]);
+        }
+    }
+  }
+}
+
+template <int MATH>
+enkf_status analysis_res_go(const NnArgs& p, const typename Lp<MATH>::e_t* Bp, int ldk, hipStream_t s) {
+  typedef typename Lp<MATH>::e_t E;
+  const size_t lds = (size_t)RT_ROWS * (ldk + 8) * sizeof(E);
+  static std::atomic<bool> attr{false};          // set once; setting it twice is harmless
+  if (!attr.load(std::memory_order_acquire)) {
+    if (hipFuncSetAttribute((const void*)analysis_res_kernel<MATH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)((size_t)RT_ROWS * (kResMaxK + 8) * sizeof(E))) != hipSuccess)
+      return fail(ENKF_ERR_HIP, "analysis product: cannot set the LDS size");
+    attr.store(true, std::memory_order_release);
+  }
+  const int64_t blocks = (p.n + RT_ROWS - 1) / RT_ROWS;
+  if (blocks > 0x7fffffff) return fail(ENKF_ERR_NOT_SUPPORTED, "analysis product: too many rows for the grid");
+  analysis_res_kernel<MATH><<<(unsigned)blocks, RT_NT, lds, s>>>(p, Bp, ldk);
+  ENKF_HIP_CHECK(hipGetLastError());
+  return ENKF_SUCCESS;
+}
+
 template <int MATH>
 void tn_launch(dim3 grid, hipStream_t s, int64_t n, int a, int m, const float* A, int64_t lda, const float* B,
                int64_t ldb, double* partial, int64_t rpc, int tiles_m, bool vec) {
@@ -489,6 +682,14 @@ enkf_status nn_launch(hipStream_t s, int mode, NnArgs p) {
   if ((p.m <= 128 ? rows : (p.n + 127) / 128) * 8 * ((p.m + 127) / 128) > 0x7fffffff)
     return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
   const bool vec = ((uintptr_t)p.A % 16) == 0 && (p.lda % 4) == 0 && (p.n % 4) == 0;
+  if constexpr (Lp<MATH>::PARTS == 1) {
+    // the analysis with many rows: the row tile stays in the LDS for every
+    // output column (the tiled kernel re-reads it per column tile)
+    if (mode == NN_ANALYSIS && p.K <= kResMaxK && p.m == p.K && p.n >= 64 * 1024) {
+      enkf_status st = analysis_res_go<MATH>(p, Bp, ldk, s);
+      return st;
+    }
+  }
   if (p.m <= 128) {
     if (mode == NN_ANALYSIS) nn_go<MATH, NN_ANALYSIS, 64, 128>(p, Bp, ldk, stride, vec, s);
     else nn_go<MATH, NN_UPDATE, 64, 128>(p, Bp, ldk, stride, vec, s);

@@ -100,3 +100,37 @@ def test_analysis_many_row_tiles(prec, math, N, tol):
     rows = np.concatenate([np.arange(64), np.random.default_rng(N).choice(n_state, 384, replace=False),
                            np.arange(n_state - 64, n_state)])
     _check(XA[rows], XB[rows], oracle.analysis(XB[rows], V, Z), tol)
+
+
+@pytest.mark.parametrize("math,n_state,N", [("bf16", 131072, 1024), ("bf16", 65536 + 37, 1000), ("f16", 70001, 96),
+                                            ("bf16", 65600, 20)])
+def test_analysis_16bit_resident_tile(math, n_state, N):
+    """The analysis product on one-pass 16-bit inputs with many state rows
+    (the kernel that keeps each 64-row tile of the centred ensemble in the
+    LDS for all output columns): against the FP64 oracle's update of the same
+    FP32 ensemble on 512 sampled rows (both ends of a ragged last tile
+    included) and over all rows by the increment norm. Inputs rounded to
+    16 bits: 2e-2 (BF16) / 5e-3 (FP16) of the largest increment."""
+    import torch
+    pk = _pk()
+    print(f"analysis {math} n_state={n_state} N={N}", flush=True)
+    g = np.random.default_rng(n_state + N)
+    n_obs = 4096
+    XB32 = (8.0 + g.standard_normal((n_state, N))).astype(np.float32).astype(np.float64)
+    V = np.asfortranarray(g.standard_normal((n_obs, N)) * 0.05)
+    V -= V.mean(axis=1, keepdims=True)
+    Z = np.asfortranarray(g.standard_normal((n_obs, N)))
+    r = np.full(n_obs, 1.0)
+    plan = pk.Plan(dev(r), dev(V, torch.float32), algo="blocked")
+    XA = host(plan.analysis_ex(dev(XB32, torch.float32), dev(Z, torch.float32), math=math))
+    torch.cuda.synchronize()
+    V32 = V.astype(np.float32).astype(np.float64)
+    Z32 = Z.astype(np.float32).astype(np.float64)
+    rows = np.unique(np.concatenate([g.choice(n_state, 500, replace=False), np.arange(6), n_state - 1 - np.arange(6)]))
+    ref = oracle.analysis(XB32[rows], V32, Z32)
+    inc, inco = XA[rows] - XB32[rows], ref - XB32[rows]
+    err = float(np.max(np.abs(inc - inco)) / np.max(np.abs(inco)))
+    tol = 2e-2 if math == "bf16" else 5e-3
+    print({"max_err": err}, flush=True)
+    assert err < tol
+    assert np.all(np.isfinite(XA))
