@@ -452,191 +452,236 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
 
 // ---------------------------------------------------------------- analysis, row tile resident
 // X^A = X^B + (X^B - xbar 1^T) (s G) with one-pass 16-bit inputs (BF16 or
-// F16) and K = N <= kResMaxK: a block owns 64 rows of X^B and keeps them,
-// centred and rounded, in the LDS for every output column, so X^B is read
-// from memory for the row means, once more to stage the tile and once for
-// the epilogue's X^B (the last two mostly from the last-level cache), and
-// X^A is written once. 4 waves; wave w computes the 64-column output groups
-// w, w + 4, ... as 4 x 4 MFMA tiles of 16 x 16 over K (64 x 64 per wave),
-// the right factor's fragments coming straight from the L2 two steps ahead
-// of their use, the tile's from the LDS. The MFMA result rows run along the
-// output columns and its columns along the output rows, so each lane group
-// reads and writes 16 consecutive rows of X^B / X^A.
+// F16), K = N <= kResMaxK and X^A's columns the members (m = K): X^B is read
+// from memory once and X^A written once. A block owns 64 rows; wave w owns
+// the members (= output columns) [128 w, 128 w + 128) and loads them into
+// registers, lane (a, b) = (l % 16, l / 16) taking rows 4a .. 4a + 3 of the
+// 32 members 128 w + 32 b + z (16-byte loads, 256 contiguous bytes of a
+// column per 16 lanes). The row means are reduced across lanes and waves;
+// the centred rows, rounded to the input type, go to the LDS as the MFMA's
+// row operand, resident for every output column. Each wave then forms its
+// 64 x 128 output as two groups of 4 x 4 MFMA tiles of 16 x 16 over K, the
+// right factor's fragments streamed from the L2 (fragment-ordered, 1 KB per
+// wave load, a two-stage register ring). The accumulators go through a small
+// per-wave LDS buffer, 8 columns at a time, back to the load layout, where
+// the registers still hold X^B for the sum, and X^A leaves in 256-byte
+// column runs again. The right factor's columns are permuted (see
+// res_frag_index) so that an MFMA tile's half holds exactly the 8 columns
+// the load layout needs next.
 constexpr int RT_ROWS = 64;
-constexpr int RT_NT = 256;
-constexpr int kResMaxK = 1152;
+constexpr int RT_CPW = 128;                // members per wave
+constexpr int RT_MAXW = 8;
+constexpr int kResMaxK = RT_CPW * RT_MAXW;
+constexpr int RT_TCOLS = 8;                // columns per transpose piece
+constexpr int RT_TLD = RT_ROWS + 4;        // column stride (floats) of a transpose buffer: spreads the banks
+
+// Position of the right factor's element (k, c) in the fragment-ordered copy.
+// Column c: wave w = c / 128, u = c % 128 = 32 b + 2 pi + d (the load layout:
+// lane quarter b, piece pi in [0, 16), d in {0, 1}); piece pi = 8 h + 2 i + e
+// is half e of MFMA column tile i of group h, whose lane p = 8 e + 2 b + d.
+// Fragment (tile T = 8 w + 4 h + i, k chunk kc) is 512 elements, lane l's 8
+// values (k = 32 kc + 8 (l / 16) + 0..7, column slot l % 16) contiguous.
+__device__ __forceinline__ int64_t res_frag_index(int k, int c, int nkc) {
+  const int w = c / RT_CPW, u = c % RT_CPW;
+  const int b = u / 32, z = u % 32, pi = z / 2, d = z % 2;
+  const int h = pi / 8, i = (pi % 8) / 2, e = pi % 2;
+  const int pl = 8 * e + 2 * b + d;
+  const int64_t tile = 8 * w + 4 * h + i;
+  return ((tile * nkc + k / 32) * 64 + 16 * ((k % 32) / 8) + pl) * 8 + k % 8;
+}
 
 template <int MATH>
-__global__ __launch_bounds__(RT_NT, 1) void analysis_res_kernel(NnArgs p, const typename Lp<MATH>::e_t* __restrict__ Bp,
-                                                               int ldk) {
+__global__ __launch_bounds__(256) void split_res_kernel(int K, int m, const double* __restrict__ Bm, int64_t ldb,
+                                                        double scale, typename Lp<MATH>::e_t* __restrict__ Bf, int kp,
+                                                        int ncols) {
+  typedef typename Lp<MATH>::e_t E;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)kp * ncols) return;
+  const int k = (int)(e % kp), c = (int)(e / kp);
+  const float x = (k < K && c < m) ? (float)(scale * Bm[k + (int64_t)c * ldb]) : 0.f;
+  E part[1];
+  Lp<MATH>::conv(x, part);
+  Bf[res_frag_index(k, c, kp / 32)] = part[0];
+}
+
+template <int MATH>
+__global__ __launch_bounds__(64 * RT_MAXW, 1) void analysis_res_kernel(NnArgs p, const typename Lp<MATH>::e_t* __restrict__ Bf,
+                                                                      int kp) {
   typedef Lp<MATH> P;
   typedef typename P::e_t E;
   typedef typename P::v_t VT;
   static_assert(P::PARTS == 1, "one-pass inputs only");
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
-  const int K = p.K;
-  const int kp = ldk;                              // K padded to 32 (the split factor is zero there)
-  const int lds_ld = kp + 8;                       // row stride of the tile in elements
-  E* As = reinterpret_cast<E*>(lds_raw);
+  __shared__ double red[RT_MAXW][RT_ROWS];
   __shared__ double mean[RT_ROWS];
-  const float* __restrict__ A = static_cast<const float*>(p.A);
+  const int K = p.K, nw = blockDim.x / kWave;
+  const int lds_ld = kp + 8;                       // tile row stride in elements
+  E* As = reinterpret_cast<E*>(lds_raw);
   const int t = threadIdx.x, l = t % kWave, w = t / kWave;
+  float* tb = reinterpret_cast<float*>(lds_raw + (size_t)RT_ROWS * lds_ld * sizeof(E)) + w * RT_TCOLS * RT_TLD;
+  const int a = l % 16, b = l / 16;                // load layout
+  const int pq = l % 16, q = l / 16;               // MFMA layout
   const int64_t row0 = (int64_t)blockIdx.x * RT_ROWS;
-  // Passes 1 and 2 read 16-byte row chunks: thread t takes rows 4 (t % 16)
-  // .. + 3 (clamped; rows past n are not stored) and members t / 16 + 16 q,
-  // sixteen loads in flight, so a block keeps 64 KB of X^B in flight.
-  const int rg = t % 16, mq = t / 16;
-  const int64_t rbase = row0 + 4 * rg;
-  // a 16-byte load where the four rows are inside and aligned; else each row
-  // clamped to the last one (its values are never stored)
-  const bool vec = ((uintptr_t)A % 16) == 0 && (p.lda % 4) == 0 && rbase + 3 < p.n;
-  auto load4 = [&](int kk) -> f4v {
-    const float* col = A + (int64_t)kk * p.lda;
-    if (vec) return *reinterpret_cast<const f4v*>(col + rbase);
-    f4v v;
+  const int64_t r4 = row0 + 4 * a;
+  const int cw = RT_CPW * w + 32 * b;              // this lane's first member
+  const float* __restrict__ A = static_cast<const float*>(p.A);
+  float* __restrict__ Cout = static_cast<float*>(p.Cout);
+  const bool vin = ((uintptr_t)A % 16) == 0 && (p.lda % 4) == 0 && r4 + 3 < p.n;
+  const bool vout = ((uintptr_t)Cout % 16) == 0 && (p.ldo % 4) == 0 && r4 + 3 < p.n;
+  // 1. X^B rows 4a .. + 3, members cw .. cw + 31 (clamped past K and n; those are never used)
+  f4v xs[32];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = col[min(rbase + e, p.n - 1)];
-    return v;
-  };
-  // 1. row means over the K members
-  double sum[4] = {0.0, 0.0, 0.0, 0.0};
-  {
-    int kk = mq;
-    for (; kk + 15 * 16 < K; kk += 16 * 16) {
-      f4v x[16];
+  for (int z = 0; z < 32; ++z) {
+    const float* col = A + (int64_t)min(cw + z, K - 1) * p.lda;
+    if (vin) {
+      xs[z] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(col + r4));
+    } else {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) x[u] = load4(kk + 16 * u);
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) sum[e] += (double)x[u][e];
-    }
-    for (; kk < K; kk += 16) {
-      const f4v x = load4(kk);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) sum[e] += (double)x[e];
+      for (int e = 0; e < 4; ++e) xs[z][e] = col[min(r4 + e, p.n - 1)];
     }
   }
-  __shared__ double red[16][RT_ROWS];
+  // 2. row means in FP64: lane sums, then over the four lane quarters, then over the waves
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int e = 0; e < 4; ++e) red[mq][4 * rg + e] = sum[e];
+  for (int z = 0; z < 32; ++z)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) s[e] += cw + z < K ? (double)xs[z][e] : 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    s[e] += __shfl_xor(s[e], 16);
+    s[e] += __shfl_xor(s[e], 32);
+  }
+  if (b == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[w][4 * a + e] = s[e];
+  }
   __syncthreads();
   if (t < RT_ROWS) {
     double tot = 0.0;
-#pragma unroll
-    for (int z = 0; z < 16; ++z) tot += red[z][t];
+    for (int z = 0; z < nw; ++z) tot += red[z][t];
     mean[t] = tot / (double)K;
   }
   __syncthreads();
-  // 2. the centred tile, rounded to the input type: chunks of 8 members
-  //    c = mq, mq + 16, ... (members past K are zero), two chunks per pass
-  double mu[4];
+  // 3. the centred tile, rounded to the input type (the FP64 mean split into
+  //    two floats: x - mean to FP32 accuracy); members past K are zero
 #pragma unroll
-  for (int e = 0; e < 4; ++e) mu[e] = mean[4 * rg + e];
-  for (int c = mq; c < kp / 8; c += 32) {
-    f4v x[2][8];
+  for (int e = 0; e < 4; ++e) {
+    const double mu = mean[4 * a + e];
+    const float mh = (float)mu, ml = (float)(mu - (double)mh);
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) x[h][u] = load4(min(8 * (c + 16 * h) + u, K - 1));
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k0 = 8 * (c + 16 * h);
-      if (k0 >= kp) break;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
+    for (int c8 = 0; c8 < 4; ++c8) {
+      const int k0 = cw + 8 * c8;
+      if (k0 < kp) {
         VT v;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           E part[1];
-          P::conv(k0 + u < K ? (float)((double)x[h][u][e] - mu[e]) : 0.f, part);
+          P::conv(k0 + u < K ? (xs[8 * c8 + u][e] - mh) - ml : 0.f, part);
           v[u] = part[0];
         }
-        *reinterpret_cast<VT*>(&As[(4 * rg + e) * lds_ld + k0]) = v;
+        *reinterpret_cast<VT*>(&As[(4 * a + e) * lds_ld + k0]) = v;
       }
     }
   }
   __syncthreads();
-  // 3. products and epilogue, 64 output columns at a time per wave
-  const float* __restrict__ Cin = static_cast<const float*>(p.Cin);
-  float* __restrict__ Cout = static_cast<float*>(p.Cout);
+  // 4. products, two groups of 64 columns, and the epilogue through tb
   const E* arow[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) arow[j] = As + (16 * j + l % 16) * lds_ld + 8 * (l / 16);
-  const int ngroups = (p.m + 63) / 64;
-  for (int g = w; g < ngroups; g += 4) {
-    const int c0 = 64 * g;
-    const E* bcol[4];
+  for (int j = 0; j < 4; ++j) arow[j] = As + (16 * j + pq) * lds_ld + 8 * q;
+  const int nkc = kp / 32;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bcol[i] = Bp + (int64_t)(c0 + 16 * i + l % 16) * ldk + 8 * (l / 16);
+  for (int h = 0; h < 2; ++h) {
     mf_f4 acc[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[j][i] = mf_f4{0.f, 0.f, 0.f, 0.f};
+    const E* bb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bb[i] = Bf + (int64_t)(8 * w + 4 * h + i) * nkc * 512 + l * 8;
+    VT bq[2][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bq[0][i] = ld8<VT>(bb[i]);
+      bq[1][i] = ld8<VT>(bb[i] + 512 * min(1, nkc - 1));
+    }
+    for (int kc = 0; kc < nkc; kc += 2) {
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        if (kc + st < nkc) {                       // nkc odd: the second stage of the last pair is empty
+          VT ro[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) ro[j] = ld8<VT>(arow[j] + 32 * (kc + st));
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[j][i] = P::mma(ro[j], bq[st][i], acc[j][i]);
+          // the chunk two ahead (past the end: the last chunk again, unused)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) bq[st][i] = ld8<VT>(bb[i] + 512 * min(kc + st + 2, nkc - 1));
+        }
+      }
+    }
+    // acc[j][i] element r: row 16 j + 4 q + r, column slot (h, i, pq): member
+    // cw' + 2 pi + d of lane quarter b' with pq = 8 e + 2 b' + d, pi = 8 h + 2 i + e
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
-    VT b0[4], b1[4], b2[4];
+      for (int e = 0; e < 2; ++e) {
+        const int pi = 8 * h + 2 * i + e;
+        if (pq / 8 == e) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      b0[i] = ld8<VT>(bcol[i]);
-      b1[i] = ld8<VT>(bcol[i] + min(32, kp - 32));
-    }
-    for (int kk = 0; kk < kp; kk += 32) {
-      const int k2 = min(kk + 64, kp - 32);        // past the end: the last chunk again, unused
-#pragma unroll
-      for (int i = 0; i < 4; ++i) b2[i] = ld8<VT>(bcol[i] + k2);
-      VT ro[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) ro[j] = ld8<VT>(arow[j] + kk);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = P::mma(b0[i], ro[j], acc[i][j]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        b0[i] = b1[i];
-        b1[i] = b2[i];
-      }
-    }
-    // epilogue: acc[i][j] element r = output (row 16 j + l % 16, column 16 i + 4 (l / 16) + r)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float cin[4][4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t row = min(row0 + 16 * j + l % 16, p.n - 1);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int col = min(c0 + 16 * i + 4 * (l / 16) + r, p.m - 1);
-          cin[j][r] = Cin[row + (int64_t)col * p.ldc];
+          for (int j = 0; j < 4; ++j) *reinterpret_cast<mf_f4*>(&tb[(pq % 8) * RT_TLD + 16 * j + 4 * q]) = acc[j][i];
         }
-      }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+        for (int d = 0; d < 2; ++d) {
+          const f4v v = *reinterpret_cast<const f4v*>(&tb[(2 * b + d) * RT_TLD + 4 * a]);
+          const int c = cw + 2 * pi + d;
+          f4v o;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int col = c0 + 16 * i + 4 * (l / 16) + r;
-          const int64_t row = row0 + 16 * j + l % 16;
-          if (col < p.m && row < p.n)
-            Cout[row + (int64_t)col * p.ldo] = (float)((double)cin[j][r] + (double)acc[i][j][r]);
+          for (int e2 = 0; e2 < 4; ++e2) o[e2] = (float)((double)xs[2 * pi + d][e2] + (double)v[e2]);
+          if (c < p.m) {
+            float* dst = Cout + (int64_t)c * p.ldo;
+            if (vout) {
+              __builtin_nontemporal_store(o, reinterpret_cast<f4v*>(dst + r4));
+            } else {
+#pragma unroll
+              for (int e2 = 0; e2 < 4; ++e2)
+                if (r4 + e2 < p.n) dst[r4 + e2] = o[e2];
+            }
+          }
         }
-    }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
   }
 }
 
 template <int MATH>
-enkf_status analysis_res_go(const NnArgs& p, const typename Lp<MATH>::e_t* Bp, int ldk, hipStream_t s) {
+enkf_status analysis_res_go(const NnArgs& p, hipStream_t s) {
   typedef typename Lp<MATH>::e_t E;
-  const size_t lds = (size_t)RT_ROWS * (ldk + 8) * sizeof(E);
+  E* Bf = static_cast<E*>(p.bws);
+  const int kp = (p.K + 31) / 32 * 32;
+  const int nw = (p.K + RT_CPW - 1) / RT_CPW, ncols = nw * RT_CPW;
+  const int64_t total = (int64_t)kp * ncols;
+  split_res_kernel<MATH><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(p.K, p.m, p.Bm, p.ldb, p.scale, Bf, kp, ncols);
+  ENKF_HIP_CHECK(hipGetLastError());
+  const size_t lds = (size_t)RT_ROWS * (kp + 8) * sizeof(E) + (size_t)nw * RT_TCOLS * RT_TLD * sizeof(float);
   static std::atomic<bool> attr{false};          // set once; setting it twice is harmless
   if (!attr.load(std::memory_order_acquire)) {
+    const size_t most = (size_t)RT_ROWS * (kResMaxK + 8) * sizeof(E) + (size_t)RT_MAXW * RT_TCOLS * RT_TLD * sizeof(float);
     if (hipFuncSetAttribute((const void*)analysis_res_kernel<MATH>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)((size_t)RT_ROWS * (kResMaxK + 8) * sizeof(E))) != hipSuccess)
+                            (int)most) != hipSuccess)
       return fail(ENKF_ERR_HIP, "analysis product: cannot set the LDS size");
     attr.store(true, std::memory_order_release);
   }
   const int64_t blocks = (p.n + RT_ROWS - 1) / RT_ROWS;
   if (blocks > 0x7fffffff) return fail(ENKF_ERR_NOT_SUPPORTED, "analysis product: too many rows for the grid");
-  analysis_res_kernel<MATH><<<(unsigned)blocks, RT_NT, lds, s>>>(p, Bp, ldk);
+  analysis_res_kernel<MATH><<<(unsigned)blocks, kWave * nw, lds, s>>>(p, Bf, kp);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }
@@ -676,20 +721,20 @@ enkf_status nn_launch(hipStream_t s, int mode, NnArgs p) {
   E* Bp = static_cast<E*>(p.bws);
   const int ldk = nn_bt_rows(p.K), cols = nn_bt_cols(p.m);
   const int64_t stride = (int64_t)ldk * cols;
+  if constexpr (Lp<MATH>::PARTS == 1) {
+    // the analysis with many rows: X^B read once, the row tile resident in
+    // the LDS for every output column (the tiled kernel re-reads it per
+    // column tile and reads X^B again for the sum)
+    if (mode == NN_ANALYSIS && p.K <= kResMaxK && p.m == p.K && p.n >= 64 * 1024 && p.Cin == p.A &&
+        p.ldc == p.lda)
+      return analysis_res_go<MATH>(p, s);
+  }
   split_b_kernel<MATH><<<(unsigned)((stride + 255) / 256), 256, 0, s>>>(p.K, p.m, p.Bm, p.ldb, p.scale, Bp, ldk, cols);
   ENKF_HIP_CHECK(hipGetLastError());
   const int64_t rows = (p.n + 63) / 64;
   if ((p.m <= 128 ? rows : (p.n + 127) / 128) * 8 * ((p.m + 127) / 128) > 0x7fffffff)
     return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
   const bool vec = ((uintptr_t)p.A % 16) == 0 && (p.lda % 4) == 0 && (p.n % 4) == 0;
-  if constexpr (Lp<MATH>::PARTS == 1) {
-    // the analysis with many rows: the row tile stays in the LDS for every
-    // output column (the tiled kernel re-reads it per column tile)
-    if (mode == NN_ANALYSIS && p.K <= kResMaxK && p.m == p.K && p.n >= 64 * 1024) {
-      enkf_status st = analysis_res_go<MATH>(p, Bp, ldk, s);
-      return st;
-    }
-  }
   if (p.m <= 128) {
     if (mode == NN_ANALYSIS) nn_go<MATH, NN_ANALYSIS, 64, 128>(p, Bp, ldk, stride, vec, s);
     else nn_go<MATH, NN_UPDATE, 64, 128>(p, Bp, ldk, stride, vec, s);
