@@ -21,7 +21,7 @@
 //
 // Layout: column-major, threads own consecutive row chunks of VW elements
 // (16-byte loads), a block owns COLS columns of one tile of LV_THREADS*VW*RPT
-// rows or, past kLvMaxRowBlocks tiles, of several consecutive tiles (the
+// rows or, past lv_max_row_blocks tiles, of several consecutive tiles (the
 // partials it sums and leaves are per block, so their number stays bounded).
 #include "enkf_internal.h"
 
@@ -41,7 +41,12 @@ constexpr int LV_COLS_STREAM = 4;
 constexpr int LV_RPT_STREAM = 4;
 template <bool STREAM> constexpr int lv_cols() { return STREAM ? LV_COLS_STREAM : LV_COLS; }
 template <bool STREAM> constexpr int lv_rpt() { return STREAM ? LV_RPT_STREAM : LV_RPT; }
-constexpr int64_t kLvMaxRowBlocks = 256;
+// Row blocks of a launch at most: 256, and 512 from 2048 tiles up (n >= 2^21
+// FP64 rows). c3 (n = 2^21, N = 256) factor + solve: 624 ms with 256 (each
+// block walking 4 tiles), 606 with 512 and 640, 614 with 768, 621 with 1024,
+// 625 with 384; n = 2^20, N = 96: 41.1 ms with 256, 41.7 with 512. A function
+// of n alone, so that every launch of a sweep has the same partial layout.
+inline int64_t lv_max_row_blocks(int64_t tiles) { return tiles >= 2048 ? 512 : 256; }
 
 template <typename T, int VW> struct VecT;
 template <> struct VecT<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
@@ -332,12 +337,13 @@ enkf_status launch_t(const LevelArgs& a, hipStream_t s) {
 int level_vw(enkf_dtype dt) { return dt == ENKF_F64 ? 2 : 4; }
 
 // Row blocks of a level launch: one tile of LV_THREADS*VW*LV_RPT rows each,
-// up to kLvMaxRowBlocks; past that a block walks several consecutive tiles,
+// up to lv_max_row_blocks; past that a block walks several consecutive tiles,
 // so the previous launch's partials that every block sums stay few.
 int level_row_blocks(enkf_dtype, int vw, int64_t n) {
   const int64_t rpb = (int64_t)LV_THREADS * vw * LV_RPT;
   const int64_t tiles = (n + rpb - 1) / rpb;
-  const int64_t tpb = (tiles + kLvMaxRowBlocks - 1) / kLvMaxRowBlocks;
+  const int64_t cap = lv_max_row_blocks(tiles);
+  const int64_t tpb = (tiles + cap - 1) / cap;
   return (int)((tiles + tpb - 1) / tpb);
 }
 
