@@ -16,10 +16,12 @@ def _pk():
 
 
 # 600,007 (odd: one row per load) and 600,008 rows give more row tiles than
-# the grid's row blocks, so each block walks several tiles
+# the grid's row blocks, so each block walks several tiles; 2,100,007 and
+# 2,100,008 rows pass 2048 row tiles (512 row blocks), and their 18 columns
+# exceed the last-level cache (the streamed, non-temporal layout)
 @pytest.mark.parametrize("n,N,nrhs", [(1, 1, 1), (5, 3, 2), (7, 1, 3), (1000, 17, 17), (4099, 33, 5),
                                       (16384, 96, 96), (70001, 40, 40), (3, 50, 50), (600007, 9, 9),
-                                      (600008, 9, 5)])
+                                      (600008, 9, 5), (2100007, 9, 9), (2100008, 9, 9)])
 def test_solve_fp64_matches_oracle(n, N, nrhs):
     import torch
     print(f"solve fp64 n={n} N={N} nrhs={nrhs}", flush=True)
@@ -50,7 +52,7 @@ def test_solve_fp32_matches_oracle(n, N):
 
 
 @pytest.mark.parametrize("n,N,nrhs", [(1, 1, 1), (5, 3, 2), (4099, 33, 5), (16384, 96, 96), (70001, 40, 40),
-                                      (3, 50, 50), (1002, 7, 11), (600008, 9, 9)])
+                                      (3, 50, 50), (1002, 7, 11), (600008, 9, 9), (2100008, 9, 9)])
 def test_fused_factor_solve_matches_oracle_and_split_path(n, N, nrhs):
     """One level loop over [U, Z] (enkf_sm_factor_solve): parity with the
     oracle, and bitwise the same Z and pivots as refactor + solve (every
