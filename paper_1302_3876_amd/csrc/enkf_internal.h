@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,21 @@ const char* status_name(enkf_status s);
     if (_e != hipSuccess)                                                                 \
       return ::enkf::fail(ENKF_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
   } while (0)
+
+// Raises a kernel's dynamic-LDS limit to `bytes` once per device (the
+// attribute belongs to the kernel on the current device); `done` holds one
+// bit per device index below 64 (larger indices set it on every call).
+inline enkf_status set_dynamic_lds(std::atomic<uint64_t>& done, const void* kernel, size_t bytes,
+                                   const char* what) {
+  int dev = 0;
+  ENKF_HIP_CHECK(hipGetDevice(&dev));
+  const uint64_t bit = dev >= 0 && dev < 64 ? (uint64_t)1 << dev : 0;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return ENKF_SUCCESS;
+  if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+    return fail(ENKF_ERR_HIP, what);
+  done.fetch_or(bit, std::memory_order_release);
+  return ENKF_SUCCESS;
+}
 
 // Records event pairs around launches of one kernel class and accumulates the
 // algorithmic bytes and flops those launches move (measurement only).

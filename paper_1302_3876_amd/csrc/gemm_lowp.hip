@@ -671,14 +671,11 @@ enkf_status analysis_res_go(const NnArgs& p, hipStream_t s) {
   split_res_kernel<MATH><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(p.K, p.m, p.Bm, p.ldb, p.scale, Bf, kp, ncols);
   ENKF_HIP_CHECK(hipGetLastError());
   const size_t lds = (size_t)RT_ROWS * (kp + 8) * sizeof(E) + (size_t)nw * RT_TCOLS * RT_TLD * sizeof(float);
-  static std::atomic<bool> attr{false};          // set once; setting it twice is harmless
-  if (!attr.load(std::memory_order_acquire)) {
-    const size_t most = (size_t)RT_ROWS * (kResMaxK + 8) * sizeof(E) + (size_t)RT_MAXW * RT_TCOLS * RT_TLD * sizeof(float);
-    if (hipFuncSetAttribute((const void*)analysis_res_kernel<MATH>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)most) != hipSuccess)
-      return fail(ENKF_ERR_HIP, "analysis product: cannot set the LDS size");
-    attr.store(true, std::memory_order_release);
-  }
+  static std::atomic<uint64_t> attr{0};
+  const size_t most = (size_t)RT_ROWS * (kResMaxK + 8) * sizeof(E) + (size_t)RT_MAXW * RT_TCOLS * RT_TLD * sizeof(float);
+  enkf_status st = set_dynamic_lds(attr, (const void*)analysis_res_kernel<MATH>, most,
+                                   "analysis product: cannot set the LDS size");
+  if (st != ENKF_SUCCESS) return st;
   const int64_t blocks = (p.n + RT_ROWS - 1) / RT_ROWS;
   if (blocks > 0x7fffffff) return fail(ENKF_ERR_NOT_SUPPORTED, "analysis product: too many rows for the grid");
   analysis_res_kernel<MATH><<<(unsigned)blocks, kWave * nw, lds, s>>>(p, Bf, kp);

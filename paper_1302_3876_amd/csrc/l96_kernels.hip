@@ -74,13 +74,10 @@ __global__ __launch_bounds__(L96_NT) void l96_rk4_kernel(int n, double* __restri
 template <int PER>
 enkf_status l96_go(int n, int m, double* X, int64_t ldx, int nsteps, double F, double dt, hipStream_t s) {
   const size_t lds = 2 * sizeof(double) * (size_t)n;
-  static std::atomic<bool> attr{false};           // set once; setting it twice is harmless
-  if (!attr.load(std::memory_order_acquire)) {
-    if (hipFuncSetAttribute((const void*)l96_rk4_kernel<PER>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(2 * sizeof(double) * L96_NT * PER)) != hipSuccess)
-      return fail(ENKF_ERR_HIP, "l96_forecast: cannot set the LDS size");
-    attr.store(true, std::memory_order_release);
-  }
+  static std::atomic<uint64_t> attr{0};
+  enkf_status st = set_dynamic_lds(attr, (const void*)l96_rk4_kernel<PER>, 2 * sizeof(double) * L96_NT * PER,
+                                   "l96_forecast: cannot set the LDS size");
+  if (st != ENKF_SUCCESS) return st;
   l96_rk4_kernel<PER><<<(unsigned)m, L96_NT, lds, s>>>(n, X, ldx, nsteps, F, dt);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
