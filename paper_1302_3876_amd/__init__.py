@@ -101,6 +101,7 @@ def lib():
     L.enkf_local_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(LocalDesc), vp, vp, vp, vp]
     L.enkf_local_analysis.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, i64, vp]
     L.enkf_local_sync.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.enkf_local_get_path.argtypes = [vp, ctypes.POINTER(i32)]
     L.enkf_local_destroy.argtypes = [vp]
     L.enkf_local_destroy.restype = None
     L.enkf_mfma_peak.argtypes = [ctypes.c_int, ctypes.POINTER(dbl)]
@@ -112,7 +113,7 @@ def lib():
     for name in ("enkf_sm_validate_desc", "enkf_build_vd", "enkf_sm_init", "enkf_sm_init_block_r", "enkf_sm_refactor",
                  "enkf_sm_refactor_block_r", "enkf_sm_factor_solve", "enkf_sm_solve", "enkf_analysis",
                  "enkf_analysis_ex", "enkf_localized_analysis", "enkf_sm_get_info", "enkf_sm_get_pivots", "enkf_sm_get_tuning", "enkf_sm_solve_noalloc", "enkf_sm_set_timing", "enkf_sm_get_timing",
-                 "enkf_local_init", "enkf_local_analysis", "enkf_local_sync"):
+                 "enkf_local_init", "enkf_local_analysis", "enkf_local_sync", "enkf_local_get_path"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -426,16 +427,23 @@ def enkf_sm_solve_noalloc(r, V, D, Z=None, algo: str = "plain", math: Optional[s
     return (Z, inf.as_dict()) if info else Z
 
 
-class LocalPlan:
-    """Batched localized analyses (enkf_local_init / enkf_local_analysis)."""
+LOCAL_TUNE = {"default": 0, "time": 1, "stream": 2, "prefix": 3}
+LOCAL_PATH = {0: "stream", 1: "prefix"}
 
-    def __init__(self, n_glob: int, n_ens: int, n_state: int, win_start, win_len, state_idx, tune: bool = True):
+
+class LocalPlan:
+    """Batched localized analyses (enkf_local_init / enkf_local_analysis).
+    tune: True / "time" (time both paths on the first call), False /
+    "default", "stream" or "prefix" (enkf_local.h, ENKF_LOCAL_TUNE_*)."""
+
+    def __init__(self, n_glob: int, n_ens: int, n_state: int, win_start, win_len, state_idx, tune=True):
         import numpy as np
         ws = np.ascontiguousarray(win_start, dtype=np.int64)
         wl = np.ascontiguousarray(win_len, dtype=np.int64)
         si = np.ascontiguousarray(state_idx, dtype=np.int64)
         self.n_prob, self.n_ens = ws.shape[0], n_ens
-        self.desc = LocalDesc(n_glob, n_ens, n_state, self.n_prob, 1 if tune else 0)
+        code = LOCAL_TUNE[tune] if isinstance(tune, str) else (1 if tune else 0)
+        self.desc = LocalDesc(n_glob, n_ens, n_state, self.n_prob, code)
         self._handle = ctypes.c_void_p()
         _check(lib().enkf_local_init(ctypes.byref(self._handle), ctypes.byref(self.desc),
                                      ctypes.c_void_p(ws.ctypes.data), ctypes.c_void_p(wl.ctypes.data),
@@ -462,9 +470,10 @@ class LocalPlan:
         return XA
 
     def sync(self):
-        kc, nb = ctypes.c_int32(), ctypes.c_int32()
+        kc, nb, path = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().enkf_local_sync(self._handle, ctypes.byref(kc), ctypes.byref(nb)), "enkf_local_sync")
-        return {"rows_per_stage": kc.value, "blocks": nb.value}
+        _check(lib().enkf_local_get_path(self._handle, ctypes.byref(path)), "enkf_local_get_path")
+        return {"rows_per_stage": kc.value, "blocks": nb.value, "path": LOCAL_PATH[path.value]}
 
     def close(self):
         if getattr(self, "_handle", None) is not None and self._handle.value:

@@ -54,6 +54,89 @@ def test_local_matches_oracle(n_ens, n_prob, lo, hi, tune):
         assert np.allclose(g[p], ref, rtol=1e-4, atol=0)
 
 
+@pytest.mark.parametrize("path", ["stream", "prefix"])
+@pytest.mark.parametrize("n_state,n_ens,n_prob,lo,hi", [(4096, 64, 300, 16, 512), (1000, 13, 120, 1, 1000),
+                                                        (333, 64, 40, 300, 333), (4096, 2, 50, 1, 40),
+                                                        (1000, 33, 90, 1, 15)])
+def test_local_paths_match_oracle(path, n_state, n_ens, n_prob, lo, hi):
+    """Each path forced: the streaming kernel and the prefix-sum path (ring
+    lengths that are and are not multiples of the 16-row chunk, windows from
+    1 row to the whole ring, wrapping past the end, shorter than a chunk)."""
+    import torch
+    print(f"local {path} n={n_state} N={n_ens} P={n_prob} n_p in [{lo},{hi}]", flush=True)
+    w = synth.c4(n_state=n_state, n_ens=n_ens, n_prob=n_prob, lo=lo, hi=hi)
+    start, ln, pts = w.extra["win_start"], w.extra["win_len"], w.extra["state_idx"]
+    V32, D32, XB32, Vd, Dd, XBd = _inputs(w)
+    plan = _pk().LocalPlan(w.n_obs, n_ens, w.n_state, start, ln, pts, tune=path)
+    gamma = _pk().colmajor(n_prob, n_ens, torch.float64)
+    xa = plan.analysis(dev(w.r), Vd, Dd, XBd, gamma=gamma)
+    cfg = plan.sync()
+    print(cfg, flush=True)
+    assert cfg["path"] == path
+    _check(w, host(xa), V32, D32, XB32, start, ln, pts, 1e-5)
+    g = host(gamma)
+    for p in (0, n_prob // 3, n_prob - 1):
+        rows = (start[p] + np.arange(ln[p])) % w.n_obs
+        ref = oracle.sm_solve(w.r[rows], V32.astype(np.float64)[rows], D32.astype(np.float64)[rows])["gamma"]
+        assert np.allclose(g[p], ref, rtol=1e-4, atol=0)
+
+
+@pytest.mark.parametrize("path", ["stream", "prefix"])
+@pytest.mark.parametrize("kind", ["nan_v", "zero_r"])
+def test_local_bad_row_reaches_only_its_windows(path, kind):
+    """A row with a NaN in V, or with r = 0: the windows that contain it give
+    non-finite results and the plan reports NOT_SPD; every other window
+    matches the oracle (the prefix path leaves the row out of its sums)."""
+    import torch
+    print(f"local bad row {kind} {path}", flush=True)
+    pk = _pk()
+    w = synth.c4(n_state=1000, n_ens=13, n_prob=60, lo=1, hi=40)
+    start, ln, pts = w.extra["win_start"], w.extra["win_len"], w.extra["state_idx"]
+    V32, D32, XB32, _, _, XBd = _inputs(w)
+    bad = 30
+    r = w.r.copy()
+    Vb = V32.copy()
+    if kind == "nan_v":
+        Vb[bad, 3] = np.nan
+    else:
+        r[bad] = 0.0
+    plan = pk.LocalPlan(w.n_obs, 13, w.n_state, start, ln, pts, tune=path)
+    xa = host(plan.analysis(dev(r), dev(Vb, torch.float32), dev(D32, torch.float32), XBd))
+    with pytest.raises(pk.EnkfError):
+        plan.sync()
+    hit = np.array([bad in (start[p] + np.arange(ln[p])) % w.n_obs for p in range(len(start))])
+    assert 0 < hit.sum() < len(start)
+    assert not np.all(np.isfinite(xa[hit]), axis=1).any()
+    ok = ~hit
+    _check(w, xa[ok], V32, D32, XB32, start[ok], ln[ok], pts[ok], 1e-5)
+
+
+def test_local_prefix_full_size_replays_and_agrees_with_stream():
+    """c4 at full size on the prefix path: graph replays bitwise equal, the
+    oracle's increments to 1e-5, and the streaming path's to 1e-5."""
+    import torch
+    print("local c4 full size, prefix path", flush=True)
+    w = synth.c4()
+    start, ln, pts = w.extra["win_start"], w.extra["win_len"], w.extra["state_idx"]
+    V32, D32, XB32, Vd, Dd, XBd = _inputs(w)
+    r = dev(w.r)
+    pre = _pk().LocalPlan(w.n_obs, w.n_ens, w.n_state, start, ln, pts, tune="prefix")
+    xa1 = host(pre.analysis(r, Vd, Dd, XBd))
+    outs = []
+    for _ in range(3):
+        outs.append(host(pre.analysis(r, Vd, Dd, XBd)))
+        torch.cuda.synchronize()
+    assert pre.sync()["path"] == "prefix"
+    for o in outs:
+        assert np.array_equal(o, xa1)
+    _check(w, xa1, V32, D32, XB32, start, ln, pts, 1e-5)
+    st = _pk().LocalPlan(w.n_obs, w.n_ens, w.n_state, start, ln, pts, tune="stream")
+    xs = host(st.analysis(r, Vd, Dd, XBd))
+    st.sync()
+    xb = XB32.astype(np.float64)[pts]
+    assert np.abs((xs - xb) - (xa1 - xb)).max() <= 1e-5 * np.abs(xa1 - xb).max()
+
+
 def test_local_full_size_and_graph_replay():
     import torch
     print("local c4 full size", flush=True)
@@ -102,10 +185,14 @@ def test_local_leading_dimension_past_4_gib():
         view = buf.as_strided((n, n_ens), (1, ldv))
         view.copy_(torch.as_tensor(M))
         wide.append(view)
-    plan = _pk().LocalPlan(w.n_obs, n_ens, w.n_state, start, ln, pts, tune=False)
+    plan = _pk().LocalPlan(w.n_obs, n_ens, w.n_state, start, ln, pts, tune="stream")
     r = dev(w.r)
     xa_wide = host(plan.analysis(r, wide[0], wide[1], XBd))
     plan.sync()
+    pre = _pk().LocalPlan(w.n_obs, n_ens, w.n_state, start, ln, pts, tune="prefix")
+    xa_wide_pre = host(pre.analysis(r, wide[0], wide[1], XBd))
+    pre.sync()
+    _check(w, xa_wide_pre, V32, D32, XB32, start, ln, pts, 1e-5)
     del wide
     torch.cuda.empty_cache()
     xa_compact = host(plan.analysis(r, Vd, Dd, XBd))
