@@ -505,11 +505,12 @@ __global__ __launch_bounds__(256) void local_chunk_kernel(PrefixArgs a) {
     dsh[rho][i] = use ? d[u] : 0.0;
   }
   __syncthreads();
-  // thread t: rows i0 .. i0+3, columns j0 .. j0+3 of both sums (rows past
-  // the chunk are zero)
+  // thread t: rows i0 .. i0+3, columns j0 + 16 y (y < 4) of both sums (rows
+  // past the chunk are zero), so that 16 lanes store 16 consecutive columns
+  // of a row pair: 256 contiguous bytes
   double* out = a.pre + (int64_t)c * a.W;
   const int half = a.Np * a.N;
-  const int i0 = 4 * (t / 16), j0 = 4 * (t % 16);
+  const int i0 = 4 * (t / 16), j0 = t % 16;
   double sa[4][4], sq[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
@@ -522,8 +523,8 @@ __global__ __launch_bounds__(256) void local_chunk_kernel(PrefixArgs a) {
     for (int x = 0; x < 4; ++x) {
       vi[x] = vs[k][i0 + x];
       wi[x] = ws[k][i0 + x];
-      wj[x] = ws[k][j0 + x];
-      dj[x] = dsh[k][j0 + x];
+      wj[x] = ws[k][j0 + 16 * x];
+      dj[x] = dsh[k][j0 + 16 * x];
     }
 #pragma unroll
     for (int x = 0; x < 4; ++x)
@@ -534,13 +535,13 @@ __global__ __launch_bounds__(256) void local_chunk_kernel(PrefixArgs a) {
       }
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 4; x += 2)
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
-      const int i = i0 + x, j = j0 + y;
+      const int i = i0 + x, j = j0 + 16 * y;      // rows i, i + 1 of column j: one 16-byte store
       if (i < a.Np && j < a.N) {
-        out[pre_index(i, j, a.N)] = sa[x][y];
-        out[half + pre_index(i, j, a.N)] = sq[x][y];
+        *reinterpret_cast<double2*>(out + pre_index(i, j, a.N)) = double2{sa[x][y], sa[x + 1][y]};
+        *reinterpret_cast<double2*>(out + half + pre_index(i, j, a.N)) = double2{sq[x][y], sq[x + 1][y]};
       }
     }
   if (t == 0) {

@@ -98,3 +98,18 @@ def test_binding_refuses_missing_library(tmp_path):
             "try:\n    pk.lib()\nexcept RuntimeError as e:\n    print('raised', e)\n") % (ROOT, str(tmp_path / "none.so"))
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True).stdout
     assert out.startswith("raised")
+
+
+def test_local_init_rejects_unknown_tune_value():
+    """enkf_local_init validates desc.tune (ENKF_LOCAL_TUNE_*) on the host,
+    before any device call."""
+    import numpy as np
+    ws = np.zeros(1, dtype=np.int64)
+    wl = np.ones(1, dtype=np.int64)
+    si = np.zeros(1, dtype=np.int64)
+    for bad in (-1, 4, 99):
+        desc = pk.LocalDesc(100, 8, 100, 1, bad)
+        h = ctypes.c_void_p()
+        code = pk.lib().enkf_local_init(ctypes.byref(h), ctypes.byref(desc), ctypes.c_void_p(ws.ctypes.data),
+                                        ctypes.c_void_p(wl.ctypes.data), ctypes.c_void_p(si.ctypes.data), None)
+        assert code == 1 and not h.value

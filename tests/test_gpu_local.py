@@ -157,6 +157,19 @@ def test_local_full_size_and_graph_replay():
     _check(w, xa1, V32, D32, XB32, start, ln, pts, 1e-5)
 
 
+def test_local_prefix_workspace_limit():
+    """A ring whose prefix sums would exceed the 1 GiB workspace limit
+    (N = 64: 64 KiB per 16-row chunk): the forced prefix path is refused at
+    init, and the default choice takes the streaming kernel."""
+    pk = _pk()
+    n = 20 * 16384
+    start, ln, pts = [0, n - 5], [300, 300], [0, 1]
+    with pytest.raises(pk.EnkfError):
+        pk.LocalPlan(n, 64, 10, start, ln, pts, tune="prefix")
+    plan = pk.LocalPlan(n, 64, 10, start, ln, pts, tune=False)
+    assert plan.sync()["path"] == "stream"
+
+
 def test_local_rejects_bad_windows():
     pk = _pk()
     with pytest.raises(pk.EnkfError):
