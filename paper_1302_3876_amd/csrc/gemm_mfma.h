@@ -5,7 +5,9 @@
 
 namespace enkf {
 
-enum NnMode : int { NN_UPDATE = 0, NN_ANALYSIS = 1, NN_RESIDUAL = 2 };
+// NN_UPDATE64 (FP32 storage only): the updated X goes to Z64 in FP64 (Z64 =
+// X - A B, or Z64 += X - A B with z64_acc) instead of back to Cout.
+enum NnMode : int { NN_UPDATE = 0, NN_ANALYSIS = 1, NN_RESIDUAL = 2, NN_UPDATE64 = 3 };
 
 struct NnArgs {
   int64_t n;            // rows
@@ -22,6 +24,8 @@ struct NnArgs {
   void* bws;                         // workspace: Bm converted (nn_bt_bytes(K, m) bytes)
   double* part; int64_t part_cap;    // RESIDUAL, optional: per-block sums of rho^2 (capacity in doubles)
   double* sumsq;                     // RESIDUAL with part: ||rho||_F^2, the partials summed in a fixed order
+  double* Z64; int64_t ldz64;        // UPDATE64: FP64 destination of the updated X
+  int z64_acc;                       // UPDATE64: 1 adds to Z64, 0 overwrites it
   int64_t n_row_tiles;               // set by the launcher
   int n_col_tiles;                   // set by the launcher
 };

@@ -444,13 +444,13 @@ __global__ __launch_bounds__(NT, 2) void nn_kernel(NnArgs p, const T* __restrict
   double ss = 0.0;   // RESIDUAL: this thread's sum of the stored rho^2
   // RESIDUAL loads two inputs per output: its rows go in two halves, so the
   // prefetched inputs leave registers for a third wave per SIMD
-  constexpr int JG = MODE == NN_RESIDUAL && RJ % 2 == 0 ? RJ / 2 : RJ;
+  constexpr int JG = (MODE == NN_RESIDUAL || MODE == NN_UPDATE64) && RJ % 2 == 0 ? RJ / 2 : RJ;
 #pragma unroll
   for (int i = 0; i < CI; ++i) {
 #pragma unroll
   for (int jg = 0; jg < RJ; jg += JG) {
     T cin[JG][4], din[JG][4];
-    double rr[JG];
+    double rr[JG], zin[JG][4];
 #pragma unroll
     for (int jj = 0; jj < JG; ++jj) {
       const int j = jg + jj;
@@ -461,6 +461,7 @@ __global__ __launch_bounds__(NT, 2) void nn_kernel(NnArgs p, const T* __restrict
         const int col = min(col0 + c_off + 16 * i + MF::row(l, r), p.m - 1);
         cin[jj][r] = Cin[row + (int64_t)col * p.ldc];
         if constexpr (MODE == NN_RESIDUAL) din[jj][r] = Din[row + (int64_t)col * p.ldd];
+        if constexpr (MODE == NN_UPDATE64) zin[jj][r] = p.z64_acc ? p.Z64[row + (int64_t)col * p.ldz64] : 0.0;
       }
     }
 #pragma unroll
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(NT, 2) void nn_kernel(NnArgs p, const T* __restrict
         const double prod = (double)acc[i][j][r];
         const double c = (double)cin[jj][r];
         double out;
-        if constexpr (MODE == NN_UPDATE) out = c - prod;
+        if constexpr (MODE == NN_UPDATE || MODE == NN_UPDATE64) out = c - prod;
         else if constexpr (MODE == NN_ANALYSIS) out = c + prod;
         else out = (double)din[jj][r] - (rr[jj] * c + prod);
         const bool in = col < p.m && row < p.n;
@@ -487,6 +488,8 @@ __global__ __launch_bounds__(NT, 2) void nn_kernel(NnArgs p, const T* __restrict
             else Cout[row + (int64_t)col * p.ldo] = (T)out;
           }
           ss += in ? out * out : 0.0;
+        } else if constexpr (MODE == NN_UPDATE64) {
+          if (in) p.Z64[row + (int64_t)col * p.ldz64] = zin[jj][r] + out;
         } else {
           if (in) Cout[row + (int64_t)col * p.ldo] = (T)out;
         }
@@ -801,6 +804,14 @@ enkf_status nn_typed(int mode, NnArgs p, hipStream_t s) {
   ENKF_HIP_CHECK(hipGetLastError());
   const bool vec = aligned16(p.A, p.lda, sizeof(T)) && p.n % (int64_t)(16 / sizeof(T)) == 0;
   if (mode == NN_UPDATE) return nn_pick<T, NN_UPDATE>(p, Bt, ldbc, vec, s);
+  if (mode == NN_UPDATE64) {
+    if constexpr (sizeof(T) == 4) {
+      if (!p.Z64) return fail(ENKF_ERR_INVALID_ARG, "update product: no FP64 destination");
+      return nn_pick<T, NN_UPDATE64>(p, Bt, ldbc, vec, s);
+    } else {
+      return fail(ENKF_ERR_NOT_SUPPORTED, "update product into FP64: FP32 storage only");
+    }
+  }
   if (mode == NN_ANALYSIS) {
     if (p.K == p.m && p.Cin == p.A && p.ldc == p.lda && analysis_small_fits<T>(p.K))
       return analysis_small<T>(p, Bt, ldbc, s);

@@ -122,8 +122,11 @@ struct Plan {
   enkf_status block_step1(enkf_dtype dt, int m, const void* X, int64_t ldx, void* Y, int64_t ldy);
   enkf_status factor_blocked();
   // Z = (R + V V^T)^{-1} D with the blocked factor, all in the working type.
-  // step1_done: Z already holds R^{-1} D (D is not read).
-  enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool step1_done = false);
+  // step1_done: Z already holds R^{-1} D (D is not read). z64 (FP32 working
+  // type only): the last panel's update writes its result to z64 in FP64
+  // (z64 = result, or z64 += result with z64_acc) instead of back to Z.
+  enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool step1_done = false,
+                            double* z64 = nullptr, int64_t ldz64 = 0, bool z64_acc = false);
   enkf_status solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
   enkf_status solve_refined64(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
   // rho = D - W Z in FP64, ||rho||^2 into norms[0] and, with d_norm,
