@@ -272,10 +272,14 @@ def roofline_of(form, name):
         fused = "fused_sweep" in k
         c = k["fused_sweep" if fused else "solve_sweep"]
         ach = c["alg_bytes_per_launch"] / (c["avg_launch_us"] * 1e-6) / 1e9
-        # (the last template argument: a block walks one row tile)
-        traffic = traffic_record("paper_1302_3876_amd/csrc/level_kernels.hip",
-                                 "level_kernel<double, 2, false, true, true, false, false>" if fused else
-                                 "level_kernel<double, 2, false, true, false, false, false>") if name == "plain_f64" else None
+        # (the last two template arguments: a block walks several row tiles,
+        # streamed columns; c3 takes that instance of the fused sweep)
+        names = (["level_kernel<double, 2, false, true, true, true, true>",
+                  "level_kernel<double, 2, false, true, true, false, false>"] if fused else
+                 ["level_kernel<double, 2, false, true, false, false, false>"])
+        traffic = None
+        for kn in names if name == "plain_f64" else []:
+            traffic = traffic or traffic_record("paper_1302_3876_amd/csrc/level_kernels.hip", kn)
         what = "fused factor + solve sweep" if fused else "solve sweep (Z columns)"
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
