@@ -399,7 +399,7 @@ def run_c1(args, pk, torch):
            "graph": {"ms_per_step": round(ms_g, 5), "ms_median": round(med_g, 5), "ms_min": round(min_g, 5),
                      "analyses_per_s": round(1e3 / ms_g, 1)},
            "graph_equals_eager_bitwise": bool(np.array_equal(xa_graph, xa_eager)),
-           "max_increment_err_vs_oracle": inc_err, "launches_per_step": w.n_ens + 4}
+           "max_increment_err_vs_oracle": inc_err}
     plan.close()
     return w, res
 

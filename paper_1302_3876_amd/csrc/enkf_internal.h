@@ -120,6 +120,25 @@ struct LevelArgs {
 };
 
 enkf_status launch_level(enkf_dtype dt, const LevelArgs& a, hipStream_t s);
+
+// The plain factorisation and/or solve of a small FP64 system in one block
+// (the columns and V resident in the LDS); see small_sweep.hip.
+struct SmallSweepArgs {
+  int64_t n;
+  int N, nrhs;
+  const double* r;
+  const double* V; int64_t ldv;
+  const double* D; int64_t ldd;
+  double* U; int64_t ldu;                 // U columns at their levels (the plan's factor), written
+  const double* Uin;                      // solve with a stored factor (ldu): u_k and gamma_k read, U not written
+  double* Z; int64_t ldz;                 // may alias D (D is read before Z is written)
+  double* gamma;                          // the N pivots
+  unsigned* status;
+};
+constexpr size_t kSmallSweepMaxLds = 56 * 1024;   // dynamic LDS: with the 8 KiB of h_k, the default 64 KiB
+constexpr int64_t kSmallSweepMaxRows = 1024;       // rows of h_k
+size_t small_sweep_lds_bytes(int64_t n, int N, int nrhs);
+enkf_status launch_small_sweep(const SmallSweepArgs& a, hipStream_t s);
 // gamma[k] = 1 + sum of column `col` of partials (last level of a factorisation).
 enkf_status launch_gamma_from_partials(const double* part, int nb, int col, double* gamma_out, unsigned* status,
                                        hipStream_t s);

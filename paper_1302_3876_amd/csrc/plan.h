@@ -128,6 +128,8 @@ struct Plan {
   enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool step1_done = false,
                             double* z64 = nullptr, int64_t ldz64 = 0, bool z64_acc = false);
   enkf_status solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
+  bool small_plain(int nrhs) const;
+  enkf_status small_sweep(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool solve_only);
   enkf_status solve_refined64(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
   // rho = D - W Z in FP64, ||rho||^2 into norms[0] and, with d_norm,
   // ||D||^2 into norms[1] (constant over one solve, so formed once). With

@@ -404,6 +404,7 @@ enkf_status Plan::diag_solve(int nrhs, const void* D, int64_t ldd, const void* Z
 // ------------------------------------------------------------------ plain
 enkf_status Plan::factor_plain() {
   if (pivot) return sweep_pivot(0, nullptr, 0, nullptr, 0);
+  if (small_plain(0)) return small_sweep(0, nullptr, 0, nullptr, 0, false);
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
   const int w = level_vw(desc.dtype);
@@ -464,6 +465,7 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
   if (nrhs == 0) return ENKF_SUCCESS;
+  if (small_plain(nrhs) && small_plain(0)) return small_sweep(nrhs, D, ldd, Z, ldz, true);
   const int w = level_vw(desc.dtype);
   const int vw = (n % w == 0 && vec_ok(U, ldu, w, es) && vec_ok(V, ldv, w, es) && vec_ok(D, ldd, w, es) &&
                   vec_ok(Z, ldz, w, es)) ? w : 1;
@@ -534,11 +536,51 @@ enkf_status Plan::solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int
 // gamma_k, applies h_k to every active column and leaves the products with
 // v_{k+1}. Z lives in the columns after U during the loop; the last level
 // writes it to the caller's buffer. Leaves the same factor as factor_plain.
+// A small FP64 system (no pivoting, diagonal R): the factorisation (nrhs =
+// 0), the fused factorisation + solve, or a solve with the stored factor, in
+// one launch of small_sweep_kernel.
+bool Plan::small_plain(int nrhs) const {
+  return desc.dtype == ENKF_F64 && !pivot && !block_r && desc.n_obs <= kSmallSweepMaxRows &&
+         small_sweep_lds_bytes(desc.n_obs, desc.n_ens, nrhs) <= kSmallSweepMaxLds;
+}
+
+enkf_status Plan::small_sweep(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool solve_only) {
+  const int64_t n = desc.n_obs;
+  const int N = desc.n_ens;
+  SmallSweepArgs a{};
+  a.n = n;
+  a.N = N;
+  a.nrhs = nrhs;
+  a.r = r;
+  a.V = static_cast<const double*>(V);
+  a.ldv = ldv;
+  a.D = static_cast<const double*>(D);
+  a.ldd = ldd;
+  a.U = static_cast<double*>(U);
+  a.ldu = ldu;
+  a.Uin = solve_only ? static_cast<const double*>(U) : nullptr;
+  a.Z = static_cast<double*>(Z);
+  a.ldz = ldz;
+  a.gamma = gamma;
+  a.status = status;
+  const double cols = solve_only ? nrhs : N + nrhs;
+  TimedLaunch tl(&timing, stream, solve_only ? KC_SOLVE_SWEEP : (nrhs ? KC_FUSED_SWEEP : KC_INIT_SWEEP),
+                 8.0 * n * (2.0 * cols + N + (solve_only ? N : 0)) + 8.0 * n, 4.0 * n * N * cols);
+  return launch_small_sweep(a, stream);
+}
+
 enkf_status Plan::factor_solve_plain(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz) {
   const int64_t n = desc.n_obs;
   const int N = desc.n_ens;
   if (nrhs == 0) return factor_plain();
   if (pivot) return sweep_pivot(nrhs, D, ldd, Z, ldz);
+  if (small_plain(nrhs)) return small_sweep(nrhs, D, ldd, Z, ldz, false);
+  if (small_plain(0)) {
+    // the factor fits the single-block path but [U, Z] does not: factor
+    // there and solve with the level launches, as refactor + solve would
+    enkf_status st = factor_plain();
+    return st != ENKF_SUCCESS ? st : solve_plain(nrhs, D, ldd, Z, ldz);
+  }
   // One loop over [U, Z] saves a launch per level, but its per-level working
   // set, (N - k + nrhs) columns, can exceed the 256 MiB last-level (MALL)
   // cache, while the separate U and Z loops each stay inside it when their

@@ -6,6 +6,8 @@ between replays and new inputs copied into the captured buffers, must equal
 the eager result bitwise. The plans are created on the capturing stream
 (a plan's stream is fixed at init); solves without info enqueue only
 kernels and device-to-device copies."""
+import gc
+
 import numpy as np
 import pytest
 
@@ -51,6 +53,7 @@ def test_graph_replays_equal_eager(algo, n_state, N):
             step()
             eager.append((host(Z), host(XA)))
         s.synchronize()
+        gc.collect()             # no plan of an earlier test may be freed inside the capture
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
             step()

@@ -19,9 +19,14 @@ def _pk():
 # the grid's row blocks, so each block walks several tiles; 2,100,007 and
 # 2,100,008 rows pass 2048 row tiles (512 row blocks), and their 18 columns
 # exceed the last-level cache (the streamed, non-temporal layout)
+# (64, 32, 48) fills the single-block path's 56 KiB of LDS exactly
+# (n (2N + nrhs) doubles); (65, 32, 48) is one row past it; 1024 rows is its
+# row limit, 1025 one past
 @pytest.mark.parametrize("n,N,nrhs", [(1, 1, 1), (5, 3, 2), (7, 1, 3), (1000, 17, 17), (4099, 33, 5),
                                       (16384, 96, 96), (70001, 40, 40), (3, 50, 50), (600007, 9, 9),
-                                      (600008, 9, 5), (2100007, 9, 9), (2100008, 9, 9)])
+                                      (600008, 9, 5), (2100007, 9, 9), (2100008, 9, 9), (64, 32, 48),
+                                      (65, 32, 48), (20, 20, 20), (200, 7, 1),
+                                      (1024, 2, 1), (1025, 2, 1)])
 def test_solve_fp64_matches_oracle(n, N, nrhs):
     import torch
     print(f"solve fp64 n={n} N={N} nrhs={nrhs}", flush=True)
@@ -52,7 +57,8 @@ def test_solve_fp32_matches_oracle(n, N):
 
 
 @pytest.mark.parametrize("n,N,nrhs", [(1, 1, 1), (5, 3, 2), (4099, 33, 5), (16384, 96, 96), (70001, 40, 40),
-                                      (3, 50, 50), (1002, 7, 11), (600008, 9, 9), (2100008, 9, 9)])
+                                      (3, 50, 50), (1002, 7, 11), (600008, 9, 9), (2100008, 9, 9), (64, 32, 48),
+                                      (65, 32, 48), (20, 20, 20)])
 def test_fused_factor_solve_matches_oracle_and_split_path(n, N, nrhs):
     """One level loop over [U, Z] (enkf_sm_factor_solve): parity with the
     oracle, and bitwise the same Z and pivots as refactor + solve (every
@@ -93,10 +99,11 @@ def test_fused_factor_solve_fp32_alias_and_zero_rhs():
     assert np.array_equal(host(plan.solve(dev(D, torch.float32))), Zs)
 
 
-def test_unaligned_leading_dimension_and_alias():
+@pytest.mark.parametrize("n", [1001, 101])     # 101: the single-block path (Z aliases D in its LDS copy)
+def test_unaligned_leading_dimension_and_alias(n):
     import torch
     pk = _pk()
-    n, N = 1001, 9
+    N = 9
     r, V, D = synth.small_vd(n, N, seed=5)
     Vp = pk.colmajor(n + 1, N)[:n]           # ld = n + 1 (odd): scalar path
     Vp.copy_(torch.as_tensor(V))

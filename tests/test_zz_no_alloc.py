@@ -6,6 +6,7 @@ second smaller (the scratch keeps the first call's contents), for the plain
 and the blocked algorithms; a captured call replayed equals the eager one;
 a problem too large for the scratch is refused before any launch."""
 import ctypes
+import gc
 
 import numpy as np
 import pytest
@@ -58,6 +59,7 @@ def test_noalloc_captured_replays_equal_eager():
         pk.enkf_sm_solve_noalloc(rd, Vd, Dd, Z)
         s.synchronize()
         ze = host(Z)
+        gc.collect()             # no plan of an earlier test may be freed inside the capture
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
             pk.enkf_sm_solve_noalloc(rd, Vd, Dd, Z)
