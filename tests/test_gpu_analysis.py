@@ -63,6 +63,24 @@ def test_analysis_fp32_storage(n_state, N):
     _check(XA, XB32, oracle.analysis(XB32, V, Z), 2e-5)
 
 
+@pytest.mark.parametrize("n_state,n_obs,N", [(4096, 100, 16), (4097, 100, 16), (256, 20, 64), (300, 50, 8),
+                                             (40, 20, 20)])
+def test_analysis_fp64_small_systems(n_state, n_obs, N):
+    """Few observations and members (the c1 shape among them), ragged state
+    row counts; a second call on the same plan gives the same result."""
+    import torch
+    print(f"analysis fp64 small n_state={n_state} n_obs={n_obs} N={N}", flush=True)
+    pk = _pk()
+    XB, V, Z, r = _inputs(n_state, n_obs, N, seed=n_state + 3 * N)
+    plan = pk.Plan(dev(r), dev(V))
+    ref = oracle.analysis(XB, V, Z)
+    XA = host(plan.analysis(dev(XB), dev(Z)))
+    XA2 = host(plan.analysis(dev(XB), dev(Z)))
+    torch.cuda.synchronize()
+    _check(XA, XB, ref, 1e-11)
+    assert np.array_equal(XA, XA2)
+
+
 def test_analysis_in_place_output_and_reuse():
     """A second call on other data gives that data's update (the persistent
     kernel keeps no state between calls)."""
