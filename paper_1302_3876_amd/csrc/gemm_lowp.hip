@@ -425,6 +425,7 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
 #pragma unroll
   for (int i = 0; i < CI; ++i) {
     float cin[RJ][4];
+    double zin[RJ][4];                            // UPDATE64: the FP64 destination's values (when it accumulates)
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
       const int64_t row = min(row0 + r_off + 16 * j + l % 16, rlim - 1);
@@ -432,6 +433,7 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
       for (int r = 0; r < 4; ++r) {
         const int col = min(col0 + c_off + 16 * i + 4 * (l / 16) + r, p.m - 1);
         cin[j][r] = Cin[row + (int64_t)col * p.ldc];
+        if constexpr (MODE == NN_UPDATE64) zin[j][r] = p.z64_acc ? p.Z64[row + (int64_t)col * p.ldz64] : 0.0;
       }
     }
 #pragma unroll
@@ -443,8 +445,12 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
         double prod = (double)acc[i][j][r];
         if constexpr (P::has_scaled) prod += (double)acc2[i][j][r] * (double)kLoScale;
         const double c = (double)cin[j][r];
-        const double out = (MODE == NN_UPDATE) ? c - prod : c + prod;
-        if (col < p.m && row < p.n) Cout[row + (int64_t)col * p.ldo] = (float)out;
+        const double out = (MODE == NN_ANALYSIS) ? c + prod : c - prod;
+        if constexpr (MODE == NN_UPDATE64) {
+          if (col < p.m && row < p.n) p.Z64[row + (int64_t)col * p.ldz64] = zin[j][r] + out;
+        } else {
+          if (col < p.m && row < p.n) Cout[row + (int64_t)col * p.ldo] = (float)out;
+        }
       }
   }
   }
@@ -732,6 +738,19 @@ enkf_status nn_launch(hipStream_t s, int mode, NnArgs p) {
   if ((p.m <= 128 ? rows : (p.n + 127) / 128) * 8 * ((p.m + 127) / 128) > 0x7fffffff)
     return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
   const bool vec = ((uintptr_t)p.A % 16) == 0 && (p.lda % 4) == 0 && (p.n % 4) == 0;
+  if (mode == NN_UPDATE64) {
+    // the last panel update of a mixed solve into the FP64 solution (the
+    // FP32-range one-pass and three-part BF16 inputs)
+    if constexpr (MATH == ENKF_MATH_BF16 || MATH == ENKF_MATH_BF16X3) {
+      if (!p.Z64) return fail(ENKF_ERR_INVALID_ARG, "update product: no FP64 destination");
+      if (p.m <= 128) nn_go<MATH, NN_UPDATE64, 64, 128>(p, Bp, ldk, stride, vec, s);
+      else nn_go<MATH, NN_UPDATE64, 128, 128>(p, Bp, ldk, stride, vec, s);
+      ENKF_HIP_CHECK(hipGetLastError());
+      return ENKF_SUCCESS;
+    } else {
+      return fail(ENKF_ERR_NOT_SUPPORTED, "update product into FP64: FP32, BF16 and BF16x3 inputs only");
+    }
+  }
   if (p.m <= 128) {
     if (mode == NN_ANALYSIS) nn_go<MATH, NN_ANALYSIS, 64, 128>(p, Bp, ldk, stride, vec, s);
     else nn_go<MATH, NN_UPDATE, 64, 128>(p, Bp, ldk, stride, vec, s);

@@ -5,8 +5,9 @@
 
 namespace enkf {
 
-// NN_UPDATE64 (FP32 storage only): the updated X goes to Z64 in FP64 (Z64 =
-// X - A B, or Z64 += X - A B with z64_acc) instead of back to Cout.
+// NN_UPDATE64 (FP32 storage; FP32, BF16 or BF16x3 inputs): the updated X
+// goes to Z64 in FP64 (Z64 = X - A B, or Z64 += X - A B with z64_acc)
+// instead of back to Cout.
 enum NnMode : int { NN_UPDATE = 0, NN_ANALYSIS = 1, NN_RESIDUAL = 2, NN_UPDATE64 = 3 };
 
 struct NnArgs {

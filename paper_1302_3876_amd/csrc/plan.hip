@@ -887,7 +887,8 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
       a.z64_acc = z64_acc ? 1 : 0;
       TimedLaunch tl(&timing, stream, KC_PANEL_UPDATE,
                      (double)(bl + nrhs) * n * wes + (z64_acc ? 16.0 : 8.0) * n * nrhs, 2.0 * n * bl * nrhs);
-      st = launch_nn(ENKF_F32, NN_UPDATE64, a, stream);
+      st = desc.math == ENKF_MATH_F32 ? launch_nn(ENKF_F32, NN_UPDATE64, a, stream)
+                                      : launch_nn_lowp(desc.math, NN_UPDATE64, a, stream);
       if (st != ENKF_SUCCESS) return st;
       continue;
     }
@@ -921,11 +922,11 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
   }
   st = launch_convert(n, nrhs, static_cast<const double*>(D), ldd, W, ldu, scale, r, status, stream);
   if (st != ENKF_SUCCESS) return st;
-  // FP32 panels: the last panel update of each solve writes (or adds) its
-  // result to Z in FP64 itself; the narrow forms widen it in a pass of
-  // their own (the FP16 forms also undo their scaling there)
+  // FP32 and BF16 / BF16x3 panels: the last panel update of each solve
+  // writes (or adds) its result to Z in FP64 itself; the FP16 forms widen
+  // it in a pass of their own, where they also undo their scaling
   double* Zd = static_cast<double*>(Z);
-  const bool fused = desc.math == ENKF_MATH_F32;
+  const bool fused = desc.math == ENKF_MATH_F32 || desc.math == ENKF_MATH_BF16 || desc.math == ENKF_MATH_BF16X3;
   st = fused ? solve_blocked(nrhs, W, ldu, W, ldu, true, Zd, ldz, false) : solve_blocked(nrhs, W, ldu, W, ldu, true);
   if (st != ENKF_SUCCESS) return st;
   if (!fused) {
