@@ -123,6 +123,15 @@ enkf_status launch_level(enkf_dtype dt, const LevelArgs& a, hipStream_t s);
 
 // The plain factorisation and/or solve of a small FP64 system in one block
 // (the columns and V resident in the LDS); see small_sweep.hip.
+// Scale of a residual block: its root mean square (1 when it is zero or
+// when no sum of squares is given). The FP16 refinement divides the
+// narrowed right-hand side by it and multiplies the correction back.
+__device__ __forceinline__ double rms_scale(const double* sumsq, double count) {
+  if (!sumsq) return 1.0;
+  const double s = sqrt(sumsq[0] / count);
+  return (s > 0.0 && s < 1e300) ? s : 1.0;
+}
+
 struct SmallSweepArgs {
   int64_t n;
   int N, nrhs;

@@ -422,6 +422,8 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
   // epilogue: inputs loaded first (clamped, branch-free), stores predicated
   float* __restrict__ Cout = static_cast<float*>(p.Cout);
   const float* __restrict__ Cin = static_cast<const float*>(p.Cin);
+  double zsc = 1.0;                               // UPDATE64: the FP16 forms' rms scale
+  if constexpr (MODE == NN_UPDATE64) zsc = rms_scale(p.z64_sumsq, (double)p.n * p.m);
 #pragma unroll
   for (int i = 0; i < CI; ++i) {
     float cin[RJ][4];
@@ -447,7 +449,8 @@ __global__ __launch_bounds__(NT, 2) void nn_lowp_kernel(NnArgs p, const typename
         const double c = (double)cin[j][r];
         const double out = (MODE == NN_ANALYSIS) ? c + prod : c - prod;
         if constexpr (MODE == NN_UPDATE64) {
-          if (col < p.m && row < p.n) p.Z64[row + (int64_t)col * p.ldz64] = zin[j][r] + out;
+          if (col < p.m && row < p.n)
+            p.Z64[row + (int64_t)col * p.ldz64] = zin[j][r] + zsc * out;
         } else {
           if (col < p.m && row < p.n) Cout[row + (int64_t)col * p.ldo] = (float)out;
         }
@@ -739,17 +742,12 @@ enkf_status nn_launch(hipStream_t s, int mode, NnArgs p) {
     return fail(ENKF_ERR_NOT_SUPPORTED, "nn product: grid too large");
   const bool vec = ((uintptr_t)p.A % 16) == 0 && (p.lda % 4) == 0 && (p.n % 4) == 0;
   if (mode == NN_UPDATE64) {
-    // the last panel update of a mixed solve into the FP64 solution (the
-    // FP32-range one-pass and three-part BF16 inputs)
-    if constexpr (MATH == ENKF_MATH_BF16 || MATH == ENKF_MATH_BF16X3) {
-      if (!p.Z64) return fail(ENKF_ERR_INVALID_ARG, "update product: no FP64 destination");
-      if (p.m <= 128) nn_go<MATH, NN_UPDATE64, 64, 128>(p, Bp, ldk, stride, vec, s);
-      else nn_go<MATH, NN_UPDATE64, 128, 128>(p, Bp, ldk, stride, vec, s);
-      ENKF_HIP_CHECK(hipGetLastError());
-      return ENKF_SUCCESS;
-    } else {
-      return fail(ENKF_ERR_NOT_SUPPORTED, "update product into FP64: FP32, BF16 and BF16x3 inputs only");
-    }
+    // the last panel update of a mixed solve into the FP64 solution
+    if (!p.Z64) return fail(ENKF_ERR_INVALID_ARG, "update product: no FP64 destination");
+    if (p.m <= 128) nn_go<MATH, NN_UPDATE64, 64, 128>(p, Bp, ldk, stride, vec, s);
+    else nn_go<MATH, NN_UPDATE64, 128, 128>(p, Bp, ldk, stride, vec, s);
+    ENKF_HIP_CHECK(hipGetLastError());
+    return ENKF_SUCCESS;
   }
   if (p.m <= 128) {
     if (mode == NN_ANALYSIS) nn_go<MATH, NN_ANALYSIS, 64, 128>(p, Bp, ldk, stride, vec, s);

@@ -5,9 +5,9 @@
 
 namespace enkf {
 
-// NN_UPDATE64 (FP32 storage; FP32, BF16 or BF16x3 inputs): the updated X
-// goes to Z64 in FP64 (Z64 = X - A B, or Z64 += X - A B with z64_acc)
-// instead of back to Cout.
+// NN_UPDATE64 (FP32 storage; FP32 or narrow inputs): the updated X goes to
+// Z64 in FP64 (Z64 = s (X - A B), or Z64 += s (X - A B) with z64_acc; s the
+// rms scale of the FP16 forms, else 1) instead of back to Cout.
 enum NnMode : int { NN_UPDATE = 0, NN_ANALYSIS = 1, NN_RESIDUAL = 2, NN_UPDATE64 = 3 };
 
 struct NnArgs {
@@ -27,6 +27,7 @@ struct NnArgs {
   double* sumsq;                     // RESIDUAL with part: ||rho||_F^2, the partials summed in a fixed order
   double* Z64; int64_t ldz64;        // UPDATE64: FP64 destination of the updated X
   int z64_acc;                       // UPDATE64: 1 adds to Z64, 0 overwrites it
+  const double* z64_sumsq;           // UPDATE64, optional: the result is multiplied by rms_scale(z64_sumsq, n m)
   int64_t n_row_tiles;               // set by the launcher
   int n_col_tiles;                   // set by the launcher
 };

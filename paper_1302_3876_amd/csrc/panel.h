@@ -20,13 +20,12 @@ enkf_status launch_panel_apply(int b, int m, const double* S, const double* Pr, 
 
 // FP64 -> FP32 copy divided by the rms of X (sumsq: device ||X||_F^2, or
 // NULL for no scaling) and, with r, by r_i row by row (Step 1 fused; bad r_i
-// latch NOT_SPD in status); FP32 -> FP64 copy or accumulation multiplied back.
+// latch NOT_SPD in status). The way back to FP64 is the last panel update of
+// each solve, which multiplies by the same rms.
 enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float* Y, int64_t ldy, const double* sumsq,
                            const double* r, unsigned* status, hipStream_t s);
 // Z += X, FP64.
 enkf_status launch_add(int64_t n, int m, const double* X, int64_t ldx, double* Z, int64_t ldz, hipStream_t s);
-enkf_status launch_widen(int64_t n, int m, const float* W, int64_t ldw, double* Z, int64_t ldz, bool accumulate,
-                         const double* sumsq, hipStream_t s);
 // out[0] = ||X||_F^2, or ||R^{-1} X||_F^2 when r is given (fixed-order
 // two-stage sum; part holds norm_partial_elems() doubles).
 int norm_partial_elems();

@@ -297,14 +297,6 @@ __global__ __launch_bounds__(256) void tri_apply_kernel(int b, int m, const doub
   }
 }
 
-// Scale of a residual block: its root mean square (1 when it is zero or
-// when no sum of squares is given).
-__device__ __forceinline__ double rms_scale(const double* sumsq, double count) {
-  if (!sumsq) return 1.0;
-  const double s = sqrt(sumsq[0] / count);
-  return (s > 0.0 && s < 1e300) ? s : 1.0;
-}
-
 // Y = X / scale in FP32 (scale = sqrt(sumsq / (n m)), the rms of what the
 // sum of squares was taken over, when sumsq is given), so a shrinking
 // residual stays inside the range of the narrow input types. With r, also
@@ -322,20 +314,6 @@ __global__ __launch_bounds__(256) void convert_kernel(int64_t n, int m, const do
     div *= rv;
   }
   for (int j = blockIdx.y; j < m; j += gridDim.y) Y[i + (int64_t)j * ldy] = (float)(X[i + (int64_t)j * ldx] / div);
-}
-
-// Z = scale W (accumulate == 0) or Z += scale W (accumulate == 1), W in FP32.
-__global__ __launch_bounds__(256) void widen_kernel(int64_t n, int m, const float* __restrict__ W, int64_t ldw,
-                                                    double* __restrict__ Z, int64_t ldz, int accumulate,
-                                                    const double* sumsq) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double sc = rms_scale(sumsq, (double)n * m);
-  for (int j = blockIdx.y; j < m; j += gridDim.y) {
-    const double w = sc * (double)W[i + (int64_t)j * ldw];
-    double* z = Z + i + (int64_t)j * ldz;
-    *z = accumulate ? *z + w : w;
-  }
 }
 
 // Z += X (FP64), the correction of an FP64 refinement step.
@@ -385,15 +363,6 @@ enkf_status launch_convert(int64_t n, int m, const double* X, int64_t ldx, float
   if (r && !status) return fail(ENKF_ERR_INVALID_ARG, "convert: row scaling needs the status word");
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)(m < 16 ? m : 16));
   convert_kernel<<<grid, 256, 0, s>>>(n, m, X, ldx, Y, ldy, sumsq, r, status);
-  ENKF_HIP_CHECK(hipGetLastError());
-  return ENKF_SUCCESS;
-}
-
-enkf_status launch_widen(int64_t n, int m, const float* W, int64_t ldw, double* Z, int64_t ldz, bool accumulate,
-                         const double* sumsq, hipStream_t s) {
-  if (m <= 0) return ENKF_SUCCESS;
-  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(m < 16 ? m : 16));
-  widen_kernel<<<grid, 256, 0, s>>>(n, m, W, ldw, Z, ldz, accumulate ? 1 : 0, sumsq);
   ENKF_HIP_CHECK(hipGetLastError());
   return ENKF_SUCCESS;
 }

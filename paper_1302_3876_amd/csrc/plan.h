@@ -124,9 +124,11 @@ struct Plan {
   // Z = (R + V V^T)^{-1} D with the blocked factor, all in the working type.
   // step1_done: Z already holds R^{-1} D (D is not read). z64 (FP32 working
   // type only): the last panel's update writes its result to z64 in FP64
-  // (z64 = result, or z64 += result with z64_acc) instead of back to Z.
+  // (z64 = s result, or z64 += s result with z64_acc; s = rms_scale(z64_sumsq,
+  // n nrhs), 1 without z64_sumsq) instead of back to Z.
   enkf_status solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool step1_done = false,
-                            double* z64 = nullptr, int64_t ldz64 = 0, bool z64_acc = false);
+                            double* z64 = nullptr, int64_t ldz64 = 0, bool z64_acc = false,
+                            const double* z64_sumsq = nullptr);
   enkf_status solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool sync);
   bool small_plain(int nrhs) const;
   enkf_status small_sweep(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool solve_only);

@@ -838,7 +838,7 @@ enkf_status Plan::factor_blocked() {
 
 // Z = W^{-1} D in the working type (D may be Z itself).
 enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, int64_t ldz, bool step1_done,
-                                double* z64, int64_t ldz64, bool z64_acc) {
+                                double* z64, int64_t ldz64, bool z64_acc, const double* z64_sumsq) {
   if (z64 && wdt != ENKF_F32) return fail(ENKF_ERR_NOT_SUPPORTED, "solve_blocked: FP64 destination needs FP32 panels");
   const int64_t n = desc.n_obs;
   const size_t wes = dtype_size(wdt);
@@ -885,6 +885,7 @@ enkf_status Plan::solve_blocked(int nrhs, const void* D, int64_t ldd, void* Z, i
       a.Z64 = z64;
       a.ldz64 = ldz64;
       a.z64_acc = z64_acc ? 1 : 0;
+      a.z64_sumsq = z64_sumsq;
       TimedLaunch tl(&timing, stream, KC_PANEL_UPDATE,
                      (double)(bl + nrhs) * n * wes + (z64_acc ? 16.0 : 8.0) * n * nrhs, 2.0 * n * bl * nrhs);
       st = desc.math == ENKF_MATH_F32 ? launch_nn(ENKF_F32, NN_UPDATE64, a, stream)
@@ -922,17 +923,12 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
   }
   st = launch_convert(n, nrhs, static_cast<const double*>(D), ldd, W, ldu, scale, r, status, stream);
   if (st != ENKF_SUCCESS) return st;
-  // FP32 and BF16 / BF16x3 panels: the last panel update of each solve
-  // writes (or adds) its result to Z in FP64 itself; the FP16 forms widen
-  // it in a pass of their own, where they also undo their scaling
+  // the last panel update of each solve writes (or adds) its result to Z in
+  // FP64 itself (the FP16 forms times the scale they divided by), so the
+  // correction is never stored in FP32 for a separate widening pass
   double* Zd = static_cast<double*>(Z);
-  const bool fused = desc.math == ENKF_MATH_F32 || desc.math == ENKF_MATH_BF16 || desc.math == ENKF_MATH_BF16X3;
-  st = fused ? solve_blocked(nrhs, W, ldu, W, ldu, true, Zd, ldz, false) : solve_blocked(nrhs, W, ldu, W, ldu, true);
+  st = solve_blocked(nrhs, W, ldu, W, ldu, true, Zd, ldz, false, scale);
   if (st != ENKF_SUCCESS) return st;
-  if (!fused) {
-    st = launch_widen(n, nrhs, W, ldu, Zd, ldz, false, scale, stream);
-    if (st != ENKF_SUCCESS) return st;
-  }
   const int maxit = desc.refine_max_iter;
   for (int it = 0; it <= maxit; ++it) {
     if (!sync && it == maxit) break;
@@ -951,12 +947,8 @@ enkf_status Plan::solve_mixed(int nrhs, const void* D, int64_t ldd, void* Z, int
       st = launch_convert(n, nrhs, rho, ldu, W, ldu, scale, r, status, stream);
       if (st != ENKF_SUCCESS) return st;
     }
-    st = fused ? solve_blocked(nrhs, W, ldu, W, ldu, true, Zd, ldz, true) : solve_blocked(nrhs, W, ldu, W, ldu, true);
+    st = solve_blocked(nrhs, W, ldu, W, ldu, true, Zd, ldz, true, scale);
     if (st != ENKF_SUCCESS) return st;
-    if (!fused) {
-      st = launch_widen(n, nrhs, W, ldu, Zd, ldz, true, scale, stream);
-      if (st != ENKF_SUCCESS) return st;
-    }
     last.refine_iters = it + 1;
   }
   return ENKF_SUCCESS;
