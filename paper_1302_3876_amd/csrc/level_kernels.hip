@@ -47,6 +47,13 @@ template <bool STREAM> constexpr int lv_rpt() { return STREAM ? LV_RPT_STREAM : 
 // 625 with 384; n = 2^20, N = 96: 41.1 ms with 256, 41.7 with 512. A function
 // of n alone, so that every launch of a sweep has the same partial layout.
 inline int64_t lv_max_row_blocks(int64_t tiles) { return tiles >= 2048 ? 512 : 256; }
+// Streamed launches run their row blocks in chunks of LV_CHUNK_STREAM: every
+// column group of one chunk before the next chunk (a bijection of the grid
+// onto (row block, column group); a row block keeps its XCD, as the chunk is
+// a multiple of 8). With 512 row blocks, c3 level time per solve: 603 ms
+// unchunked, 592 with chunks of 256, 622 of 128, 658 of 64; with 768 row
+// blocks 611 (chunks of 256 or 384), with 1024 599 (512) and 705 (256).
+constexpr int LV_CHUNK_STREAM = 256;
 
 template <typename T, int VW> struct VecT;
 template <> struct VecT<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
@@ -135,14 +142,24 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
   constexpr int64_t RPB = (int64_t)LV_THREADS * VW * RPT;   // rows of one tile
   const int64_t n = a.n;
   const int nb = gridDim.x;
-  int64_t tile0 = blockIdx.x, tile1 = tile0 + 1;
+  int bx = blockIdx.x, by = blockIdx.y;            // row block, column group
+  if constexpr (STREAM) {
+    if (nb % LV_CHUNK_STREAM == 0) {
+      const int64_t lin = (int64_t)blockIdx.y * nb + blockIdx.x;   // dispatch order
+      const int64_t per = (int64_t)LV_CHUNK_STREAM * gridDim.y;
+      const int64_t chunk = lin / per, rem = lin % per;
+      by = (int)(rem / LV_CHUNK_STREAM);
+      bx = (int)(chunk * LV_CHUNK_STREAM + rem % LV_CHUNK_STREAM);
+    }
+  }
+  int64_t tile0 = bx, tile1 = tile0 + 1;
   if constexpr (MULTI) {
     const int64_t tiles = (n + RPB - 1) / RPB;
     const int64_t tpb = (tiles + nb - 1) / nb;
-    tile0 = (int64_t)blockIdx.x * tpb;
+    tile0 = (int64_t)bx * tpb;
     tile1 = min(tiles, tile0 + tpb);
   }
-  const int g = blockIdx.y;
+  const int g = by;
   const int col0 = g * COLS;
   const int ncol = min(COLS, a.m - col0);
   const int t = threadIdx.x;
@@ -210,7 +227,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
     double gam;
     if constexpr (OWN_GAMMA) {
       gam = 1.0 + gam_s;
-      if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
+      if (bx == 0 && by == 0 && t == 0) {
         *a.gamma_out = gam;
         if (!(gam > 0.0) || !__builtin_isfinite(gam)) atomicOr(a.status, kStatusNotSpd);
       }
@@ -279,7 +296,7 @@ __global__ __launch_bounds__(LV_THREADS) void level_kernel(LevelArgs a) {
     double sacc = 0.0;
 #pragma unroll
     for (int w = 0; w < LV_WAVES; ++w) sacc += red[w][t];
-    a.part_out[(int64_t)phys(col0 + t) * nb + blockIdx.x] = sacc;
+    a.part_out[(int64_t)phys(col0 + t) * nb + bx] = sacc;
   }
 }
 
