@@ -18,7 +18,10 @@ def _pk():
 # 600,007 (odd: one row per load) and 600,008 rows give more row tiles than
 # the grid's row blocks, so each block walks several tiles; 2,100,007 and
 # 2,100,008 rows pass 2048 row tiles (512 row blocks), and their 18 columns
-# exceed the last-level cache (the streamed, non-temporal layout)
+# exceed the last-level cache (the streamed, non-temporal layout);
+# 2,097,147 (2^21 - 5) and 4,194,301 (2^22 - 3) rows give exactly 512 row
+# blocks (one and eight tiles each, ragged last tile), so the streamed
+# levels run their row blocks in chunks of 256
 # (64, 32, 48) fills the single-block path's 56 KiB of LDS exactly
 # (n (2N + nrhs) doubles); (65, 32, 48) is one row past it; 1024 rows is its
 # row limit, 1025 one past
@@ -26,7 +29,7 @@ def _pk():
                                       (16384, 96, 96), (70001, 40, 40), (3, 50, 50), (600007, 9, 9),
                                       (600008, 9, 5), (2100007, 9, 9), (2100008, 9, 9), (64, 32, 48),
                                       (65, 32, 48), (20, 20, 20), (200, 7, 1),
-                                      (1024, 2, 1), (1025, 2, 1)])
+                                      (1024, 2, 1), (1025, 2, 1), (2097147, 9, 9), (4194301, 5, 5)])
 def test_solve_fp64_matches_oracle(n, N, nrhs):
     import torch
     print(f"solve fp64 n={n} N={N} nrhs={nrhs}", flush=True)
