@@ -273,8 +273,8 @@ def roofline_of(form, name):
         c = k["fused_sweep" if fused else "solve_sweep"]
         ach = c["alg_bytes_per_launch"] / (c["avg_launch_us"] * 1e-6) / 1e9
         # (the last two template arguments: a block walks several row tiles,
-        # streamed columns; c3 takes that instance of the fused sweep)
-        names = (["level_kernel<double, 2, false, true, true, true, true>",
+        # streamed columns; c3 takes the streamed instance, one tile per block)
+        names = (["level_kernel<double, 2, false, true, true, false, true>",
                   "level_kernel<double, 2, false, true, true, false, false>"] if fused else
                  ["level_kernel<double, 2, false, true, false, false, false>"])
         traffic = None

@@ -32,13 +32,15 @@ constexpr int LV_THREADS = 256;
 constexpr int LV_WAVES = LV_THREADS / kWave;
 constexpr int LV_COLS = 8;
 constexpr int LV_RPT = 2;
-// Streamed launches (columns past the last-level cache): half the columns
-// per block and twice the rows, so fewer column streams are open at once
-// (n = 2^21, 512 down to 256 columns per level, per-solve time: 8 x 2 636 ms,
-// 4 x 4 625 ms, 2 x 8 655 ms, 16 x 2 646 ms; narrower groups re-read u_k and
-// v_{k+1} more often).
-constexpr int LV_COLS_STREAM = 4;
-constexpr int LV_RPT_STREAM = 4;
+// Streamed launches (columns past the last-level cache): a quarter of the
+// columns per block and four times the rows, so fewer column streams are
+// open at once. Narrow groups re-read u_k and v_{k+1} once per group; with
+// the chunked grid order below those re-reads hit the L2. n = 2^21, 512 down
+// to 256 columns per level, level time per solve with chunks of 256: 2 x 8
+// 556-558 ms, 4 x 4 591-592, 4 x 8 598, 8 x 2 629 (unchunked: 2 x 8 655,
+// 4 x 4 603-625, 8 x 2 636, 16 x 2 646).
+constexpr int LV_COLS_STREAM = 2;
+constexpr int LV_RPT_STREAM = 8;
 template <bool STREAM> constexpr int lv_cols() { return STREAM ? LV_COLS_STREAM : LV_COLS; }
 template <bool STREAM> constexpr int lv_rpt() { return STREAM ? LV_RPT_STREAM : LV_RPT; }
 // Row blocks of a launch at most: 256, and 512 from 2048 tiles up (n >= 2^21
@@ -50,9 +52,10 @@ inline int64_t lv_max_row_blocks(int64_t tiles) { return tiles >= 2048 ? 512 : 2
 // Streamed launches run their row blocks in chunks of LV_CHUNK_STREAM: every
 // column group of one chunk before the next chunk (a bijection of the grid
 // onto (row block, column group); a row block keeps its XCD, as the chunk is
-// a multiple of 8). With 512 row blocks, c3 level time per solve: 603 ms
-// unchunked, 592 with chunks of 256, 622 of 128, 658 of 64; with 768 row
-// blocks 611 (chunks of 256 or 384), with 1024 599 (512) and 705 (256).
+// a multiple of 8). With 512 row blocks and 4 x 4 groups, c3 level time per
+// solve: 603 ms unchunked, 592 with chunks of 256, 622 of 128, 658 of 64;
+// with 768 row blocks 611 (chunks of 256 or 384), with 1024 599 (512) and
+// 705 (256). With 2 x 8 groups: 556-558 ms (256), 556 (128).
 constexpr int LV_CHUNK_STREAM = 256;
 
 template <typename T, int VW> struct VecT;

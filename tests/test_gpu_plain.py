@@ -20,8 +20,8 @@ def _pk():
 # 2,100,008 rows pass 2048 row tiles (512 row blocks), and their 18 columns
 # exceed the last-level cache (the streamed, non-temporal layout);
 # 2,097,147 (2^21 - 5) and 4,194,301 (2^22 - 3) rows give exactly 512 row
-# blocks (one and eight tiles each, ragged last tile), so the streamed
-# levels run their row blocks in chunks of 256
+# blocks (one and two streamed tiles each, ragged last tile), so the
+# streamed levels run their row blocks in chunks of 256
 # (64, 32, 48) fills the single-block path's 56 KiB of LDS exactly
 # (n (2N + nrhs) doubles); (65, 32, 48) is one row past it; 1024 rows is its
 # row limit, 1025 one past
